@@ -1,0 +1,208 @@
+/*
+ * vbcsr.h -- C ABI of the MI355X (gfx950) variable-block sparse library.
+ *
+ * The library applies an atom-centred block-sparse operator A to dense
+ * multi-vectors.  Atom i carries b_i orbitals; a stored coupling (i, j) is a
+ * dense b_i x b_j block (paper, section 2.1).  Scalar row offsets are
+ * off_0 = 0, off_{i+1} = off_i + b_i and N = off_n.  The structure is given
+ * once (block sizes, block row pointers, block column indices -- the atom
+ * graph of section 3.1 for one rank) and values may be replaced later.
+ *
+ * Layout conventions (readings of the paper, which does not fix them):
+ *   - input/output block values are in graph (CSR) order, each block
+ *     row-major (section 3.2 states row-major dense blocks for the products);
+ *   - dense multi-vectors are row-major N x nrhs arrays with a leading
+ *     dimension ld >= nrhs (element (r, c) at r*ld + c), in device memory;
+ *   - FP64 handles take double vectors, FP32 and BF16X3 handles take float.
+ *
+ * Errors: every call returns a status (VBCSR_OK or a negative code) and
+ * records a message readable through vbcsr_last_error() on the calling
+ * thread.  All argument validation happens on the host before any HIP call.
+ * Asynchronous device faults are reported as VBCSR_EHIP by a later call.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
+ * are enqueued asynchronously; the library synchronises the device only in
+ * vbcsr_create, vbcsr_set_values (host input), vbcsr_cheb_moments and
+ * vbcsr_destroy.  A handle is immutable except through vbcsr_set_values;
+ * products on different streams may run concurrently on one handle, but
+ * must not overlap a vbcsr_set_values on it.
+ */
+#ifndef VBCSR_H
+#define VBCSR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vbcsr_mat vbcsr_mat; /* opaque, owned by the library */
+
+typedef enum {
+  VBCSR_FP64 = 0,   /* FP64 values and vectors, FP64 arithmetic                  */
+  VBCSR_FP32 = 1,   /* values rounded to FP32, FP32 vectors, FP32 accumulation    */
+  VBCSR_BF16X3 = 2  /* FP32-rounded values split a = hi + lo (two BF16 each);
+                       a*x ~ hi*xh + hi*xl + lo*xh on matrix cores, FP32
+                       accumulation, FP32 vectors                                  */
+} vbcsr_prec;
+
+enum {
+  VBCSR_OK = 0,
+  VBCSR_EINVAL = -1,       /* malformed argument (null pointer, bad index, ld < nrhs ...) */
+  VBCSR_ESHAPE = -2,       /* n_values does not equal sum over blocks of b_i*b_j        */
+  VBCSR_EDUP = -3,         /* a block (i, j) appears twice in one row                   */
+  VBCSR_ENOMEM = -4,       /* device or host allocation failed                          */
+  VBCSR_EHIP = -5,         /* HIP runtime error (message holds hipGetErrorString)       */
+  VBCSR_EUNSUPPORTED = -6  /* valid but outside what this build handles                 */
+};
+
+enum { VBCSR_PATH_AUTO = 0, VBCSR_PATH_VEC = 1, VBCSR_PATH_MFMA = 2 };
+
+/* Planner options; zero fields mean "choose automatically".
+ *   path:        VBCSR_PATH_* -- force the vector-FMA or the matrix-core
+ *                kernel family for FP64/FP32 (BF16X3 always uses matrix cores);
+ *                the environment variable VBCSR_PATH={auto,vec,mfma} overrides.
+ *   nrhs_tile:   columns per pass of the vector kernel (1, 2, 4 or 8).
+ *   rows_per_wg: reserved, must be 0.                                          */
+typedef struct {
+  int32_t rows_per_wg;
+  int32_t nrhs_tile;
+  int32_t path;
+} vbcsr_plan_opts;
+
+/* Largest block size (orbitals per atom) this build accepts. */
+#define VBCSR_MAX_BLOCK 64
+
+/*
+ * vbcsr_create -- build a device operator from a block graph and values.
+ * Paper: section 3.1 (atom graph, block size per node), section 3.2
+ * (shape classes registered from the distinct (b_i, b_j); every block mapped
+ * to its place in a shape-specific buffer).
+ *
+ *   out          receives the new handle (set to NULL on failure)
+ *   n_atoms      number of atoms n >= 0 (rows and columns of the block graph)
+ *   block_sizes  host [n_atoms], 1 <= b_i <= VBCSR_MAX_BLOCK
+ *   row_ptr      host [n_atoms+1], block units, row_ptr[0] = 0, non-decreasing
+ *   col_idx      host [row_ptr[n]], 0 <= j < n, unique within a row, any order
+ *   values       host, graph order, each block row-major (double); NULL = zeros
+ *   n_values     must equal sum over blocks of b_i*b_j
+ *   prec         storage/compute precision of the handle
+ *   opts         may be NULL
+ *   stream       stream used for the initial upload (synchronised before return)
+ *
+ * The caller keeps ownership of every input array; the library deep-copies.
+ * Errors: EINVAL, ESHAPE, EDUP, EUNSUPPORTED (b_i > VBCSR_MAX_BLOCK or
+ * N > 2^31-1), ENOMEM, EHIP.
+ */
+int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
+                 const int64_t *row_ptr, const int32_t *col_idx, const double *values,
+                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream);
+
+/*
+ * vbcsr_set_values -- replace all block values, same structure.
+ *   values     n_values entries in graph order, each block row-major
+ *   on_device  0: host pointer (copied, synchronises `stream`);
+ *              1: device pointer (read by a kernel on `stream`; no sync)
+ *   dtype      0 = double, 1 = float
+ * Errors: EINVAL, ENOMEM, EHIP.
+ */
+int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream);
+
+/*
+ * vbcsr_spmm -- Y <- alpha * A * X + beta * Y.
+ * Paper: section 3.2, forward product: Y_i accumulates A_ij X_j over the
+ * stored columns j of block row i.
+ *   X   device, N x nrhs, leading dimension ldx >= nrhs, read only
+ *   Y   device, N x nrhs, leading dimension ldy >= nrhs
+ *   beta == 0 means Y is not read (NaNs in Y are ignored); an empty block row
+ *   gives Y_i = beta * Y_i.  X and Y must not overlap.
+ * Errors: EINVAL (null pointers, nrhs <= 0, ld < nrhs, overlap), EHIP.
+ */
+int vbcsr_spmm(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy,
+               int32_t nrhs, double alpha, double beta, void *stream);
+
+/*
+ * vbcsr_spmm_t -- Y <- alpha * A^T * X + beta * Y.
+ * Paper: equation (1), the adjoint product Y_j += A_ij^dagger X_i for
+ * j in J(i); values are real, so the adjoint is the transpose.  Arguments
+ * and errors as vbcsr_spmm.  No atomics: every output row has one writer.
+ */
+int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                 int32_t nrhs, double alpha, double beta, void *stream);
+
+/*
+ * vbcsr_sddmm -- dA_ij = dY_i * X_j^T on the stored blocks only.
+ * This is the gradient of sum(Y o G) with respect to the stored block values
+ * when Y = A X and dY = G (with dX = A^T G from vbcsr_spmm_t).
+ *   dY  device, N x nrhs, leading dimension lddy >= nrhs
+ *   X   device, N x nrhs, leading dimension ldx >= nrhs
+ *   dA  device, n_values entries, graph order, each block row-major; double
+ *       for FP64 handles, float otherwise.  Must not overlap dY or X.
+ * Errors: EINVAL, EHIP.
+ */
+int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X, int64_t ldx,
+                int32_t nrhs, void *dA, void *stream);
+
+/*
+ * vbcsr_cheb_workspace_bytes -- device workspace, in bytes, that
+ * vbcsr_cheb_moments needs for this handle, nrhs and degree: two N x nrhs
+ * recurrence vectors, per-workgroup FP64 partial moments and the moments.
+ * Errors: EINVAL.
+ */
+int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes);
+
+/*
+ * vbcsr_cheb_moments -- Chebyshev moments of the kernel polynomial method
+ * (paper, section 5): with T_0 = R, T_1 = A R, T_{k+1} = 2 A T_k - T_{k-1},
+ *   mu_host[k*nrhs + c] = sum_r R[r, c] * T_k[r, c],   k = 0..degree,
+ * each moment accumulated in FP64 in a fixed order (bitwise reproducible).
+ * A must already be scaled so that its spectrum lies in [-1, 1].  The vectors
+ * T_k are kept in the handle's vector type (double or float).
+ *   R          device, N x nrhs, leading dimension ldr >= nrhs
+ *   degree     >= 0
+ *   mu_host    host, (degree+1)*nrhs doubles
+ *   workspace  device, >= vbcsr_cheb_workspace_bytes() bytes, 256-byte aligned;
+ *              NULL = allocate (and free) it inside the call
+ * Synchronises `stream` (copies the moments to the host).
+ * Errors: EINVAL, ENOMEM, EHIP.
+ */
+int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
+                       int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
+                       void *stream);
+
+/*
+ * vbcsr_info -- sizes of a handle: n_rows = N (scalar rows), nnzb stored
+ * blocks, n_values = sum of b_i*b_j, n_shapes = distinct (b_i, b_j) classes.
+ * Any output pointer may be NULL.
+ */
+int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
+               int32_t *n_shapes);
+
+/*
+ * vbcsr_plan_host -- run validation and the host planner without a device
+ * (diagnostics and tests).  Inputs as vbcsr_create.
+ *   shapes       out, up to max_shapes triples (b_i, b_j, count) in ascending
+ *                (b_i, b_j); *n_shapes receives the total number of classes
+ *   fwd_pos      out [nnzb] or NULL: offset, in the forward value pages, of the
+ *                first value of every graph-order block
+ *   tr_pos       out [nnzb] or NULL: the same for the transposed pages
+ *   page_values  out or NULL: number of values in each set of pages
+ * Errors: as vbcsr_create, minus device errors.
+ */
+int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
+                    const int32_t *col_idx, int64_t n_values, int32_t *n_shapes,
+                    int32_t *shapes, int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos,
+                    int64_t *page_values);
+
+/* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
+void vbcsr_destroy(vbcsr_mat *A);
+
+/* vbcsr_last_error -- message of the last non-OK status on this thread
+ * ("" if none).  The pointer stays valid until the next call on the thread. */
+const char *vbcsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VBCSR_H */

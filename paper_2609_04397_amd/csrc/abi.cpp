@@ -1,0 +1,529 @@
+// C ABI of the variable-block sparse library: handles, validation, routing
+// and launches.  See include/vbcsr.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/vbcsr.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace vbcsr;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *where) {
+  return fail(VBCSR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, where)                         \
+  do {                                               \
+    hipError_t e_ = (expr);                          \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// Allocation counter for fault injection: VBCSR_FAIL_ALLOC_AFTER=n makes the
+// (n+1)-th device allocation of the process fail with VBCSR_ENOMEM before any
+// HIP call is made.
+std::atomic<long> g_alloc_count{0};
+
+int dev_alloc(void **p, size_t bytes) {
+  *p = nullptr;
+  const char *lim = std::getenv("VBCSR_FAIL_ALLOC_AFTER");
+  const long n = g_alloc_count.fetch_add(1);
+  if (lim && *lim && n >= std::atol(lim)) return fail(VBCSR_ENOMEM, "injected allocation failure");
+  if (bytes == 0) return VBCSR_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+    (void)hipGetLastError();
+    return fail(VBCSR_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  return VBCSR_OK;
+}
+
+template <typename T>
+int upload(T **dst, const std::vector<T> &src, hipStream_t s) {
+  int rc = dev_alloc(reinterpret_cast<void **>(dst), sizeof(T) * src.size());
+  if (rc) return rc;
+  if (!src.empty())
+    HIP_TRY(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+  return VBCSR_OK;
+}
+
+struct DevDir {
+  RowDesc *rows = nullptr;
+  int32_t *colx = nullptr;
+  void *vals = nullptr;       // double or float pages (FP64/FP32)
+  uint16_t *hi = nullptr;     // BF16 pages (BF16X3)
+  uint16_t *lo = nullptr;
+  int64_t *vbase16 = nullptr;
+  int64_t *blk_pos = nullptr;
+  int32_t *blk_k0 = nullptr;
+  int32_t *blk_prow = nullptr;
+  int64_t n_values = 0, n_values16 = 0;
+};
+
+int env_path() {
+  const char *e = std::getenv("VBCSR_PATH");
+  if (!e) return VBCSR_PATH_AUTO;
+  if (!std::strcmp(e, "vec")) return VBCSR_PATH_VEC;
+  if (!std::strcmp(e, "mfma")) return VBCSR_PATH_MFMA;
+  return VBCSR_PATH_AUTO;
+}
+
+}  // namespace
+
+struct vbcsr_mat {
+  int32_t n = 0;
+  int64_t N = 0, nnzb = 0, nnz = 0;
+  int32_t n_shapes = 0;
+  vbcsr_prec prec = VBCSR_FP64;
+  vbcsr_plan_opts opts{};
+  // graph-order structure on the device
+  int32_t *b = nullptr;
+  int32_t *off = nullptr;
+  int64_t *row_ptr = nullptr;
+  int32_t *col_idx = nullptr;
+  int32_t *blk_row = nullptr;
+  int64_t *gbase = nullptr;
+  DevDir dir[2];  // 0 = forward pages, 1 = transposed pages
+  std::vector<void *> owned;
+};
+
+namespace {
+
+size_t vec_elem(const vbcsr_mat *A) { return A->prec == VBCSR_FP64 ? 8 : 4; }
+
+template <typename T>
+int alloc_into(vbcsr_mat *A, T **p, size_t count) {
+  int rc = dev_alloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+  if (rc == VBCSR_OK && *p) A->owned.push_back(*p);
+  return rc;
+}
+
+template <typename T>
+int upload_into(vbcsr_mat *A, T **p, const std::vector<T> &v, hipStream_t s) {
+  int rc = upload(p, v, s);
+  if (rc == VBCSR_OK && *p) A->owned.push_back(*p);
+  return rc;
+}
+
+void free_all(vbcsr_mat *A) {
+  if (!A) return;
+  if (!A->owned.empty()) (void)hipDeviceSynchronize();
+  for (void *p : A->owned) (void)hipFree(p);
+  A->owned.clear();
+}
+
+// Pack graph-order values (device) into both directions' pages.
+int pack_all(vbcsr_mat *A, const void *src, int src_dtype, hipStream_t s) {
+  for (int d = 0; d < 2; ++d) {
+    DevDir &D = A->dir[d];
+    PackParams pp{};
+    pp.b = A->b;
+    pp.blk_row = A->blk_row;
+    pp.col_idx = A->col_idx;
+    pp.gbase = A->gbase;
+    pp.pos = D.blk_pos;
+    pp.k0 = D.blk_k0;
+    pp.prow = D.blk_prow;
+    pp.vbase16 = D.vbase16;
+    pp.nnzb = A->nnzb;
+    pp.transposed = d;
+    hipError_t e;
+    if (A->prec == VBCSR_BF16X3)
+      e = launch_pack(pp, src, src_dtype, D.hi, 2, D.lo, s);
+    else
+      e = launch_pack(pp, src, src_dtype, D.vals, A->prec == VBCSR_FP64 ? 0 : 1, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
+  }
+  return VBCSR_OK;
+}
+
+bool ranges_overlap(const void *a, size_t abytes, const void *b, size_t bbytes) {
+  const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t span_bytes(int64_t rows, int64_t ld, int32_t nrhs, size_t elem) {
+  if (rows <= 0) return 0;
+  return ((size_t)(rows - 1) * (size_t)ld + (size_t)nrhs) * elem;
+}
+
+int check_vectors(const vbcsr_mat *A, const void *X, int64_t ldx, const void *Y, int64_t ldy,
+                  int32_t nrhs, bool y_written) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (nrhs <= 0) return fail(VBCSR_EINVAL, "nrhs must be >= 1");
+  if (ldx < nrhs || ldy < nrhs) return fail(VBCSR_EINVAL, "leading dimension smaller than nrhs");
+  if (A->N == 0) return VBCSR_OK;
+  if (!X || !Y) return fail(VBCSR_EINVAL, "vector pointer is NULL");
+  const size_t e = vec_elem(A);
+  if (y_written && ranges_overlap(X, span_bytes(A->N, ldx, nrhs, e), Y, span_bytes(A->N, ldy, nrhs, e)))
+    return fail(VBCSR_EINVAL, "input and output vectors overlap");
+  return VBCSR_OK;
+}
+
+struct Route {
+  Kind kind;
+  int tile;
+};
+
+Route route(const vbcsr_mat *A, int32_t nrhs) {
+  int path = env_path();
+  if (path == VBCSR_PATH_AUTO) path = A->opts.path;
+  if (A->prec == VBCSR_BF16X3) return {Kind::Bf16x3, nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4};
+  bool vec = path == VBCSR_PATH_VEC || (path == VBCSR_PATH_AUTO && nrhs <= 8);
+  if (vec) {
+    int t = A->opts.nrhs_tile;
+    if (t != 1 && t != 2 && t != 4 && t != 8) t = nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8;
+    return {Kind::Vec, t};
+  }
+  return {Kind::Mfma, nrhs <= 16 ? 1 : nrhs <= 32 ? 2 : 4};
+}
+
+// One product over the panels of direction d.
+int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Yin, int64_t ldyin,
+            void *Yout, int64_t ldy, int32_t nrhs, double alpha, double beta, const void *R,
+            int64_t ldr, double *mom, hipStream_t s) {
+  const DevDir &D = A->dir[d];
+  const Route rt = route(A, nrhs);
+  hipError_t e;
+  if (A->prec == VBCSR_FP64) {
+    FwdParams<double> p{};
+    p.rows = D.rows;
+    p.nrows = A->n;
+    p.colx = D.colx;
+    p.vals = static_cast<const double *>(D.vals);
+    p.X = static_cast<const double *>(X);
+    p.ldx = ldx;
+    p.Yin = static_cast<const double *>(Yin);
+    p.ldyin = ldyin;
+    p.Yout = static_cast<double *>(Yout);
+    p.ldy = ldy;
+    p.nrhs = nrhs;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.R = static_cast<const double *>(R);
+    p.ldr = ldr;
+    p.mom = mom;
+    e = launch_spmm_f64(p, rt.kind, rt.tile, s);
+  } else {
+    FwdParams<float> p{};
+    p.rows = D.rows;
+    p.nrows = A->n;
+    p.colx = D.colx;
+    p.vals = static_cast<const float *>(D.vals);
+    p.hi = D.hi;
+    p.lo = D.lo;
+    p.vbase16 = D.vbase16;
+    p.X = static_cast<const float *>(X);
+    p.ldx = ldx;
+    p.Yin = static_cast<const float *>(Yin);
+    p.ldyin = ldyin;
+    p.Yout = static_cast<float *>(Yout);
+    p.ldy = ldy;
+    p.nrhs = nrhs;
+    p.alpha = alpha;
+    p.beta = beta;
+    p.R = static_cast<const float *>(R);
+    p.ldr = ldr;
+    p.mom = mom;
+    e = launch_spmm_f32(p, rt.kind, rt.tile, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "product kernel launch");
+  return VBCSR_OK;
+}
+
+int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
+                 int64_t n_values, HostPlan &plan) {
+  std::string err;
+  int rc = validate_graph(n, b, row_ptr, col_idx, n_values, err);
+  if (rc) return fail(rc, err);
+  build_plan(n, b, row_ptr, col_idx, plan);
+  return VBCSR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vbcsr_last_error(void) { return g_last_error.c_str(); }
+
+int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
+                    const int32_t *col_idx, int64_t n_values, int32_t *n_shapes, int32_t *shapes,
+                    int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values) {
+  HostPlan plan;
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, plan);
+  if (rc) return rc;
+  if (n_shapes) *n_shapes = (int32_t)plan.shapes.size();
+  if (shapes)
+    for (int32_t t = 0; t < std::min<int32_t>(max_shapes, (int32_t)plan.shapes.size()); ++t)
+      for (int c = 0; c < 3; ++c) shapes[3 * t + c] = plan.shapes[t][c];
+  if (fwd_pos) std::copy(plan.fwd.blk_pos.begin(), plan.fwd.blk_pos.end(), fwd_pos);
+  if (tr_pos) std::copy(plan.tr.blk_pos.begin(), plan.tr.blk_pos.end(), tr_pos);
+  if (page_values) *page_values = plan.fwd.n_values;
+  return VBCSR_OK;
+}
+
+int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
+                 const int64_t *row_ptr, const int32_t *col_idx, const double *values,
+                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream) {
+  if (!out) return fail(VBCSR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (prec != VBCSR_FP64 && prec != VBCSR_FP32 && prec != VBCSR_BF16X3)
+    return fail(VBCSR_EINVAL, "unknown precision");
+  if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA))
+    return fail(VBCSR_EINVAL, "invalid plan options");
+  HostPlan plan;
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, plan);
+  if (rc) return rc;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  vbcsr_mat *A = new vbcsr_mat();
+  A->n = n_atoms;
+  A->N = plan.N;
+  A->nnzb = plan.nnzb;
+  A->nnz = plan.nnz;
+  A->n_shapes = (int32_t)plan.shapes.size();
+  A->prec = prec;
+  if (opts) A->opts = *opts;
+
+  auto bail = [&](int code) {
+    free_all(A);
+    delete A;
+    return code;
+  };
+  std::vector<int32_t> bvec(block_sizes, block_sizes + n_atoms);
+  std::vector<int32_t> offv((size_t)n_atoms);
+  for (int32_t i = 0; i < n_atoms; ++i) offv[i] = (int32_t)plan.off[i];
+  std::vector<int64_t> rp(row_ptr, row_ptr + n_atoms + 1);
+  std::vector<int32_t> ci(col_idx, col_idx + plan.nnzb);
+  std::vector<int64_t> gb(plan.gbase.begin(), plan.gbase.end() - 1);
+  if ((rc = upload_into(A, &A->b, bvec, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->off, offv, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->row_ptr, rp, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->col_idx, ci, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->blk_row, plan.blk_row, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->gbase, gb, s))) return bail(rc);
+  for (int d = 0; d < 2; ++d) {
+    const DirPlan &P = d == 0 ? plan.fwd : plan.tr;
+    DevDir &D = A->dir[d];
+    D.n_values = P.n_values;
+    D.n_values16 = P.n_values16;
+    if ((rc = upload_into(A, &D.rows, P.rows, s))) return bail(rc);
+    if ((rc = upload_into(A, &D.colx, P.colx, s))) return bail(rc);
+    if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
+    if ((rc = upload_into(A, &D.blk_k0, P.blk_k0, s))) return bail(rc);
+    if ((rc = upload_into(A, &D.blk_prow, P.blk_prow, s))) return bail(rc);
+    if (prec == VBCSR_BF16X3) {
+      if ((rc = upload_into(A, &D.vbase16, P.vbase16, s))) return bail(rc);
+      if ((rc = alloc_into(A, &D.hi, (size_t)P.n_values16))) return bail(rc);
+      if ((rc = alloc_into(A, &D.lo, (size_t)P.n_values16))) return bail(rc);
+      if (P.n_values16) {
+        hipError_t e = hipMemsetAsync(D.hi, 0, sizeof(uint16_t) * P.n_values16, s);
+        if (e == hipSuccess) e = hipMemsetAsync(D.lo, 0, sizeof(uint16_t) * P.n_values16, s);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+      }
+    } else {
+      const size_t es = prec == VBCSR_FP64 ? 8 : 4;
+      char *p = nullptr;
+      if ((rc = alloc_into(A, &p, es * (size_t)P.n_values))) return bail(rc);
+      D.vals = p;
+    }
+  }
+  // initial values: host graph order -> device staging -> pages
+  if (plan.nnz > 0) {
+    double *stage = nullptr;
+    if ((rc = dev_alloc(reinterpret_cast<void **>(&stage), sizeof(double) * plan.nnz))) return bail(rc);
+    hipError_t e = values ? hipMemcpyAsync(stage, values, sizeof(double) * plan.nnz,
+                                           hipMemcpyHostToDevice, s)
+                          : hipMemsetAsync(stage, 0, sizeof(double) * plan.nnz, s);
+    if (e == hipSuccess) {
+      rc = pack_all(A, stage, 0, s);
+      e = hipStreamSynchronize(s);
+    }
+    (void)hipFree(stage);
+    if (rc) return bail(rc);
+    if (e != hipSuccess) return bail(hip_fail(e, "create"));
+  } else {
+    hipError_t e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "create"));
+  }
+  *out = A;
+  return VBCSR_OK;
+}
+
+int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (dtype != 0 && dtype != 1) return fail(VBCSR_EINVAL, "dtype must be 0 (double) or 1 (float)");
+  if (A->nnz == 0) return VBCSR_OK;
+  if (!values) return fail(VBCSR_EINVAL, "values is NULL");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t es = dtype == 0 ? 8 : 4;
+  if (on_device) return pack_all(A, values, dtype, s);
+  void *stage = nullptr;
+  int rc = dev_alloc(&stage, es * A->nnz);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(stage, values, es * A->nnz, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    rc = pack_all(A, stage, dtype, s);
+    e = hipStreamSynchronize(s);
+  }
+  (void)hipFree(stage);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "set_values");
+  return VBCSR_OK;
+}
+
+int vbcsr_spmm(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nrhs,
+               double alpha, double beta, void *stream) {
+  int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
+  if (rc || A->N == 0) return rc;
+  return product(A, 0, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
+                 static_cast<hipStream_t>(stream));
+}
+
+int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                 int32_t nrhs, double alpha, double beta, void *stream) {
+  int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
+  if (rc || A->N == 0) return rc;
+  return product(A, 1, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
+                 static_cast<hipStream_t>(stream));
+}
+
+int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X, int64_t ldx,
+                int32_t nrhs, void *dA, void *stream) {
+  int rc = check_vectors(A, dY, lddy, X, ldx, nrhs, false);
+  if (rc) return rc;
+  if (A->nnz == 0) return VBCSR_OK;
+  if (!dA) return fail(VBCSR_EINVAL, "dA is NULL");
+  const size_t e = vec_elem(A);
+  const size_t abytes = e * (size_t)A->nnz;
+  if (ranges_overlap(dA, abytes, dY, span_bytes(A->N, lddy, nrhs, e)) ||
+      ranges_overlap(dA, abytes, X, span_bytes(A->N, ldx, nrhs, e)))
+    return fail(VBCSR_EINVAL, "dA overlaps an input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t err;
+  if (A->prec == VBCSR_FP64) {
+    SddmmParams<double> p{A->b, A->off, A->row_ptr, A->col_idx, A->gbase, A->n,
+                          static_cast<const double *>(dY), lddy, static_cast<const double *>(X),
+                          ldx, nrhs, static_cast<double *>(dA)};
+    err = launch_sddmm_f64(p, s);
+  } else {
+    SddmmParams<float> p{A->b, A->off, A->row_ptr, A->col_idx, A->gbase, A->n,
+                         static_cast<const float *>(dY), lddy, static_cast<const float *>(X),
+                         ldx, nrhs, static_cast<float *>(dA)};
+    err = launch_sddmm_f32(p, s);
+  }
+  if (err != hipSuccess) return hip_fail(err, "sddmm kernel launch");
+  return VBCSR_OK;
+}
+
+int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes) {
+  if (!A || !bytes) return fail(VBCSR_EINVAL, "NULL argument");
+  if (nrhs <= 0) return fail(VBCSR_EINVAL, "nrhs must be >= 1");
+  if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
+  const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
+  const int64_t parts = std::max(product_workgroups(A->n), coldot_chunks(A->N));
+  // two recurrence vectors, the per-workgroup partial moments, all moments
+  *bytes = 2 * vec + 8 * parts * nrhs + 8 * (int64_t)(degree + 1) * nrhs;
+  return VBCSR_OK;
+}
+
+int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
+                       int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
+                       void *stream) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
+  if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
+  if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
+  if (!mu_host) return fail(VBCSR_EINVAL, "mu_host is NULL");
+  if (A->N > 0 && !R) return fail(VBCSR_EINVAL, "R is NULL");
+  int64_t need = 0;
+  int rc = vbcsr_cheb_workspace_bytes(A, nrhs, degree, &need);
+  if (rc) return rc;
+  if (workspace && ws_bytes < need) return fail(VBCSR_EINVAL, "workspace too small");
+  if (A->N == 0) {
+    std::fill(mu_host, mu_host + (size_t)(degree + 1) * nrhs, 0.0);
+    return VBCSR_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void *ws = workspace;
+  if (!ws && (rc = dev_alloc(&ws, (size_t)need))) return rc;
+  const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
+  const int64_t nparts = std::max(product_workgroups(A->n), coldot_chunks(A->N));
+  char *base = static_cast<char *>(ws);
+  void *Ta = base;
+  void *Tb = base + vec;
+  double *parts = reinterpret_cast<double *>(base + 2 * vec);
+  double *all_mu = parts + nparts * nrhs;
+  std::vector<double> mu((size_t)(degree + 1) * nrhs);
+  // mu_0 = <R, R>
+  int64_t nch = 0;
+  hipError_t e;
+  if (A->prec == VBCSR_FP64)
+    e = launch_coldot_f64(static_cast<const double *>(R), ldr, static_cast<const double *>(R), ldr,
+                          A->N, nrhs, parts, &nch, s);
+  else
+    e = launch_coldot_f32(static_cast<const float *>(R), ldr, static_cast<const float *>(R), ldr,
+                          A->N, nrhs, parts, &nch, s);
+  if (e == hipSuccess) e = launch_reduce_partials(parts, nch, nrhs, all_mu, s);
+  const int64_t npw = product_workgroups(A->n);
+  // T_1 = A R; T_k = 2 A T_{k-1} - T_{k-2} written over the buffer of T_{k-2}
+  // (each element is read once, by the thread that overwrites it), except at
+  // k == 2 where T_0 is the caller's R.
+  const void *prev = R;  // T_{k-2}
+  int64_t ldprev = ldr;
+  void *cur = Ta;        // T_{k-1}
+  for (int32_t k = 1; k <= degree && e == hipSuccess && rc == VBCSR_OK; ++k) {
+    if (k == 1) {
+      rc = product(A, 0, R, ldr, Ta, nrhs, Ta, nrhs, nrhs, 1.0, 0.0, R, ldr, parts, s);
+    } else {
+      void *dst = (k == 2) ? Tb : const_cast<void *>(prev);
+      rc = product(A, 0, cur, nrhs, prev, ldprev, dst, nrhs, nrhs, 2.0, -1.0, R, ldr, parts, s);
+      prev = cur;
+      ldprev = nrhs;
+      cur = dst;
+    }
+    if (rc == VBCSR_OK) e = launch_reduce_partials(parts, npw, nrhs, all_mu + (size_t)k * nrhs, s);
+  }
+  if (e == hipSuccess && rc == VBCSR_OK)
+    e = hipMemcpyAsync(mu.data(), all_mu, sizeof(double) * mu.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (!workspace) (void)hipFree(ws);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "cheb_moments");
+  std::copy(mu.begin(), mu.end(), mu_host);
+  return VBCSR_OK;
+}
+
+int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
+               int32_t *n_shapes) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (n_rows) *n_rows = A->N;
+  if (nnzb) *nnzb = A->nnzb;
+  if (n_values) *n_values = A->nnz;
+  if (n_shapes) *n_shapes = A->n_shapes;
+  return VBCSR_OK;
+}
+
+void vbcsr_destroy(vbcsr_mat *A) {
+  if (!A) return;
+  free_all(A);
+  delete A;
+}
+
+}  // extern "C"

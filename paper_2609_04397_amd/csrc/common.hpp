@@ -1,0 +1,63 @@
+// Internal definitions shared by the host planner, the ABI layer and the
+// gfx950 kernels of the variable-block sparse library.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace vbcsr {
+
+// One block row ("panel") of one direction of the operator.
+//
+// The forward direction stores block row i of A as a dense b_i x K_i panel,
+// K_i = sum of b_j over its stored blocks, column-major: panel element (p, k)
+// sits at vbase + k*b + p.  Blocks keep their identity: block (i, j) fills
+// the contiguous panel columns [k0, k0 + b_j), i.e. a contiguous run of
+// b_i*b_j values holding the block column-major.  Inside a row, blocks are
+// ordered by (b_j, j), so each shape class (b_i, b_j) of the row is one
+// contiguous run.  The transposed direction stores A^T the same way, so its
+// blocks are the untransposed source blocks, row-major.
+struct RowDesc {
+  int64_t vbase;  // first value of the panel (elements of the page type)
+  int64_t cbase;  // first entry of the panel in the column table
+  int32_t K;      // panel width (scalar columns)
+  int32_t yrow;   // first output scalar row (off_i)
+  int32_t b;      // panel height (b_i)
+  int32_t pad;
+};
+static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
+
+struct DirPlan {
+  std::vector<RowDesc> rows;     // one per atom, atom order
+  std::vector<int32_t> colx;     // per panel column: scalar row of the input vector
+  std::vector<int64_t> blk_pos;  // per graph block: page offset of its first value
+  std::vector<int32_t> blk_k0;   // per graph block: first panel column
+  std::vector<int32_t> blk_prow; // per graph block: atom whose panel holds it
+  std::vector<int64_t> vbase16;  // per atom: offset in the BF16 pages (8-column groups)
+  int64_t n_values = 0;          // values in the pages
+  int64_t n_values16 = 0;        // values in each BF16 page (panels padded to 8 columns)
+  int64_t n_cols = 0;            // entries of the column table
+};
+
+struct HostPlan {
+  int32_t n = 0;
+  int64_t N = 0, nnzb = 0, nnz = 0;
+  std::vector<int64_t> off;                   // n+1 scalar row offsets
+  std::vector<int64_t> gbase;                 // nnzb+1 graph value offsets
+  std::vector<int32_t> blk_row;               // per graph block: block row i
+  std::vector<std::array<int32_t, 3>> shapes; // (b_i, b_j, count), ascending
+  DirPlan fwd, tr;
+};
+
+// Host-side validation of a block graph; returns a VBCSR_* status and fills
+// `err` on failure.  Touches no device.
+int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
+                   int64_t n_values, std::string &err);
+
+// Build both directions of the plan (assumes validate_graph passed).
+void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
+                HostPlan &plan);
+
+}  // namespace vbcsr

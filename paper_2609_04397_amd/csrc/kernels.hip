@@ -1,0 +1,562 @@
+// gfx950 (CDNA4) kernels of the variable-block sparse library.
+//
+// Products run one 64-lane wave per panel (block row of A, or of A^T for the
+// adjoint).  Panels are column-major b x K, so a run of consecutive panel
+// values is a sequence of whole columns.  Two kernel families cover the
+// forward product Y_i = sum_j A_ij X_j (paper, section 3.2):
+//
+//  * vector FMA (few right-hand sides): lane (g, p) owns panel row p of
+//    column group g; with G = 64 / b groups, load step s reads the G*b
+//    consecutive values [s*G*b, (s+1)*G*b) -- one contiguous wave access for
+//    any block size -- and multiplies each by the X row of its column.
+//    Partial sums of one panel row meet by a tree of cross-lane shuffles.
+//  * matrix cores (many right-hand sides): the panel is the A operand of
+//    16x16x4 FP64/FP32 MFMA (M = panel rows padded to 16 in registers only,
+//    K = panel columns, N = 16 right-hand sides per tile); its 4-column slices
+//    are again contiguous in memory.  The BF16x3 form uses 16x16x32 BF16 MFMA
+//    on pages stored in 8-column groups (8 consecutive columns of one panel
+//    row are 16 contiguous bytes, the per-lane A fragment).
+//
+// Every output element has exactly one writer (no atomics), so results are
+// bitwise reproducible run to run.
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace vbcsr {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u __attribute__((ext_vector_type(8)));
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Give every XCD one contiguous range of logical workgroups so that
+// panels that share input rows (spatial neighbours) share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int nx = 8;
+  const int x = bid % nx, r = bid / nx;
+  const int q = nblocks / nx, rem = nblocks % nx;
+  return x * q + min(x, rem) + r;
+}
+
+__device__ __forceinline__ v4d mfma(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma_bf16(v8u a, v8u b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                 __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
+
+template <typename T> struct Frag;
+template <> struct Frag<double> { using type = v4d; };
+template <> struct Frag<float> { using type = v4f; };
+
+// Output row (within the 16x16 tile) of accumulator element i of the lanes
+// in quarter-wave kq.  The FP32 and BF16 16x16 tiles give each quarter-wave
+// four consecutive rows; the FP64 16x16x4 tile interleaves them with stride 4
+// (lane layout measured on gfx950).
+template <typename T> __device__ __forceinline__ int dst_row(int kq, int i);
+template <> __device__ __forceinline__ int dst_row<double>(int kq, int i) { return kq + 4 * i; }
+template <> __device__ __forceinline__ int dst_row<float>(int kq, int i) { return 4 * kq + i; }
+
+// Round-to-nearest-even FP32 -> BF16 (finite inputs) and back.
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float(((unsigned int)h) << 16);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <bool MOM>
+__device__ __forceinline__ void mom_init(double *s_mom, int nrhs) {
+  if (MOM) {
+    for (int c = threadIdx.x; c < kWaves * nrhs; c += kThreads) s_mom[c] = 0.0;
+    __syncthreads();
+  }
+}
+
+template <bool MOM>
+__device__ __forceinline__ void mom_flush(const double *s_mom, int nrhs, int wg, double *out) {
+  if (MOM) {
+    __syncthreads();
+    for (int c = threadIdx.x; c < nrhs; c += kThreads) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) t += s_mom[w * nrhs + c];
+      out[(int64_t)wg * nrhs + c] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// vector-FMA product, NR right-hand sides per pass
+// ---------------------------------------------------------------------------
+template <typename T, int NR, bool MOM>
+__global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
+  extern __shared__ double s_mom[];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = wg * kWaves + w;
+  mom_init<MOM>(s_mom, P.nrhs);
+  if (row < P.nrows) {
+    const RowDesc rd = P.rows[row];
+    const int b = rd.b, K = rd.K;
+    const int G = 64 / b;
+    const int g = lane / b;
+    const int p = lane - g * b;
+    const int GB = G * b;
+    const int nfull = K / G;          // steps in which every group has a column
+    const int rem = K - nfull * G;    // groups with a column in the tail step
+    const T *__restrict__ v = P.vals + rd.vbase + lane;
+    const int32_t *__restrict__ cx = P.colx + rd.cbase + g;
+    for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
+      const int nc = min(NR, P.nrhs - c0);
+      T acc[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) acc[c] = T(0);
+      if (g < G) {
+        const T *__restrict__ xb = P.X + c0;
+        if (nc == NR) {
+#pragma unroll 4
+          for (int s = 0; s < nfull; ++s) {
+            const T a = v[(int64_t)s * GB];
+            const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a, xp[c], acc[c]);
+          }
+          if (g < rem) {
+            const T a = v[(int64_t)nfull * GB];
+            const T *xp = xb + (int64_t)cx[nfull * G] * P.ldx;
+#pragma unroll
+            for (int c = 0; c < NR; ++c) acc[c] = fma(a, xp[c], acc[c]);
+          }
+        } else {
+          for (int s = 0; s < nfull + (g < rem ? 1 : 0); ++s) {
+            const T a = v[(int64_t)s * GB];
+            const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+#pragma unroll
+            for (int c = 0; c < NR; ++c)
+              if (c < nc) acc[c] = fma(a, xp[c], acc[c]);
+          }
+        }
+      }
+      // groups g and g + st hold partial sums of the same panel row
+      for (int st = 1; st < G; st <<= 1) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const T o = __shfl_down(acc[c], st * b, 64);
+          if ((g & (2 * st - 1)) == 0 && g + st < G) acc[c] += o;
+        }
+      }
+      double mom[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) mom[c] = 0.0;
+      if (lane < b) {
+        const int64_t r = (int64_t)rd.yrow + p;
+        T *yo = P.Yout + r * P.ldy + c0;
+        const T *yi = P.Yin + r * P.ldyin + c0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          if (c < nc) {
+            T y = T(P.alpha) * acc[c];
+            if (P.beta != 0.0) y = fma(T(P.beta), yi[c], y);
+            yo[c] = y;
+            if (MOM) mom[c] = (double)P.R[r * P.ldr + c0 + c] * (double)y;
+          }
+        }
+      }
+      if (MOM) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const double t = wave_sum(mom[c]);
+          if (lane == 0 && c < nc) s_mom[w * P.nrhs + c0 + c] += t;
+        }
+      }
+    }
+  }
+  mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32 matrix-core product, 16*NT right-hand sides per pass
+// ---------------------------------------------------------------------------
+template <typename T, int NT, bool MOM>
+__global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
+  extern __shared__ double s_mom[];
+  using V = typename Frag<T>::type;
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = wg * kWaves + w;
+  const int m = lane & 15;   // A: panel row in the tile; B and D: column in the tile
+  const int kq = lane >> 4;  // A and B: column of the 4-column slice; D: row quad
+  mom_init<MOM>(s_mom, P.nrhs);
+  if (row < P.nrows) {
+    const RowDesc rd = P.rows[row];
+    const int b = rd.b, K = rd.K;
+    const int nsteps = (K + 3) >> 2;
+    const T *__restrict__ vals = P.vals + rd.vbase;
+    const int32_t *__restrict__ cx = P.colx + rd.cbase;
+    for (int mt = 0; mt * 16 < b; ++mt) {
+      const int p = mt * 16 + m;
+      const bool prow = p < b;
+      for (int c0 = 0; c0 < P.nrhs; c0 += 16 * NT) {
+        V acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = V{};
+        for (int s = 0; s < nsteps; ++s) {
+          const int k = s * 4 + kq;
+          const bool kin = k < K;
+          const T a = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
+          const int64_t xr = kin ? (int64_t)cx[k] : 0;
+          const T *xp = P.X + xr * P.ldx + c0 + m;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int n = c0 + t * 16 + m;
+            const T x = (kin && n < P.nrhs) ? xp[t * 16] : T(0);
+            acc[t] = mfma(a, x, acc[t]);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int n = c0 + t * 16 + m;
+          double mm = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int pr = mt * 16 + dst_row<T>(kq, i);
+            if (pr < b && n < P.nrhs) {
+              const int64_t r = (int64_t)rd.yrow + pr;
+              T y = T(P.alpha) * acc[t][i];
+              if (P.beta != 0.0) y = fma(T(P.beta), P.Yin[r * P.ldyin + n], y);
+              P.Yout[r * P.ldy + n] = y;
+              if (MOM) mm += (double)P.R[r * P.ldr + n] * (double)y;
+            }
+          }
+          if (MOM) {
+            mm += __shfl_xor(mm, 16, 64);
+            mm += __shfl_xor(mm, 32, 64);
+            if (kq == 0 && n < P.nrhs) s_mom[w * P.nrhs + n] += mm;
+          }
+        }
+      }
+    }
+  }
+  mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 matrix-core product: a*x ~ ah*xh + ah*xl + al*xh, FP32 accumulation
+// ---------------------------------------------------------------------------
+template <int NT, bool MOM>
+__global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
+  extern __shared__ double s_mom[];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = wg * kWaves + w;
+  const int m = lane & 15;
+  const int kg = lane >> 4;  // 8-column group of the 32-column slice
+  mom_init<MOM>(s_mom, P.nrhs);
+  if (row < P.nrows) {
+    const RowDesc rd = P.rows[row];
+    const int b = rd.b, K = rd.K;
+    const int ngroups = (K + 7) >> 3;
+    const int nsteps = (K + 31) >> 5;
+    const int64_t vb16 = P.vbase16[row];
+    const int32_t *__restrict__ cx = P.colx + rd.cbase;
+    for (int mt = 0; mt * 16 < b; ++mt) {
+      const int p = mt * 16 + m;
+      const bool prow = p < b;
+      for (int c0 = 0; c0 < P.nrhs; c0 += 16 * NT) {
+        v4f acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = v4f{};
+        for (int s = 0; s < nsteps; ++s) {
+          const int grp = s * 4 + kg;
+          v8u ah = v8u{}, al = v8u{};
+          if (prow && grp < ngroups) {
+            const int64_t a = vb16 + (int64_t)grp * 8 * b + p * 8;
+            ah = *reinterpret_cast<const v8u *>(P.hi + a);
+            al = *reinterpret_cast<const v8u *>(P.lo + a);
+          }
+          int64_t xr[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = grp * 8 + u;
+            xr[u] = k < K ? (int64_t)cx[k] : -1;
+          }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            const int n = c0 + t * 16 + m;
+            v8u xh, xl;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const float xv = (xr[u] >= 0 && n < P.nrhs) ? P.X[xr[u] * P.ldx + n] : 0.0f;
+              const unsigned short h = bf16_rne(xv);
+              xh[u] = h;
+              xl[u] = bf16_rne(xv - bf16_to_f32(h));
+            }
+            acc[t] = mfma_bf16(ah, xh, acc[t]);
+            acc[t] = mfma_bf16(ah, xl, acc[t]);
+            acc[t] = mfma_bf16(al, xh, acc[t]);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int n = c0 + t * 16 + m;
+          double mm = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int pr = mt * 16 + dst_row<float>(kg, i);
+            if (pr < b && n < P.nrhs) {
+              const int64_t r = (int64_t)rd.yrow + pr;
+              float y = float(P.alpha) * acc[t][i];
+              if (P.beta != 0.0) y = fmaf(float(P.beta), P.Yin[r * P.ldyin + n], y);
+              P.Yout[r * P.ldy + n] = y;
+              if (MOM) mm += (double)P.R[r * P.ldr + n] * (double)y;
+            }
+          }
+          if (MOM) {
+            mm += __shfl_xor(mm, 16, 64);
+            mm += __shfl_xor(mm, 32, 64);
+            if (kg == 0 && n < P.nrhs) s_mom[w * P.nrhs + n] += mm;
+          }
+        }
+      }
+    }
+  }
+  mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
+}
+
+// ---------------------------------------------------------------------------
+// value packing: graph order (row-major blocks) -> pages
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src, int src_dtype,
+                                                   void *dst, int dst_kind, uint16_t *dst_lo) {
+  const int64_t k = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  if (k >= P.nnzb) return;
+  const int lane = threadIdx.x & 63;
+  const int i = P.blk_row[k], j = P.col_idx[k];
+  const int bi = P.b[i], bj = P.b[j];
+  const int h = P.transposed ? bj : bi;
+  const int64_t sb = P.gbase[k];
+  const int64_t pos = P.pos[k];
+  const int k0 = P.k0[k];
+  const int64_t vb16 = dst_kind == 2 ? P.vbase16[P.prow[k]] : 0;
+  for (int e = lane; e < bi * bj; e += 64) {
+    const int p = e / bj, q = e - p * bj;  // source element (p, q)
+    const double val = src_dtype == 0 ? static_cast<const double *>(src)[sb + e]
+                                      : (double)static_cast<const float *>(src)[sb + e];
+    const int r = P.transposed ? q : p;    // panel row
+    const int c = P.transposed ? p : q;    // panel column relative to k0
+    if (dst_kind == 2) {
+      const int col = k0 + c;
+      const int64_t a = vb16 + (int64_t)(col >> 3) * 8 * h + r * 8 + (col & 7);
+      const float f = (float)val;
+      const unsigned short hb = bf16_rne(f);
+      static_cast<uint16_t *>(dst)[a] = hb;
+      dst_lo[a] = bf16_rne(f - bf16_to_f32(hb));
+    } else {
+      const int64_t a = pos + (int64_t)c * h + r;
+      if (dst_kind == 0)
+        static_cast<double *>(dst)[a] = val;
+      else
+        static_cast<float *>(dst)[a] = (float)val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// block-sampled dY X^T, one wave per block row, graph-order output
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sddmm(SddmmParams<T> P) {
+  const int i = xcd_remap(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+  if (i >= P.n) return;
+  const int lane = threadIdx.x & 63;
+  const int bi = P.b[i];
+  const int64_t yoff = P.off[i];
+  for (int64_t k = P.row_ptr[i]; k < P.row_ptr[i + 1]; ++k) {
+    const int j = P.col_idx[k];
+    const int bj = P.b[j];
+    const int64_t xoff = P.off[j];
+    const int64_t base = P.gbase[k];
+    for (int e = lane; e < bi * bj; e += 64) {
+      const int p = e / bj, q = e - p * bj;
+      const T *dy = P.dY + (yoff + p) * P.lddy;
+      const T *x = P.X + (xoff + q) * P.ldx;
+      T acc = T(0);
+      for (int c = 0; c < P.nrhs; ++c) acc = fma(dy[c], x[c], acc);
+      P.dA[base + e] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// column dot products in FP64 and their fixed-order reduction
+// ---------------------------------------------------------------------------
+constexpr int kDotRows = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_coldot(const T *A, int64_t lda, const T *B, int64_t ldb,
+                                                     int64_t nrows, int32_t nrhs, double *partial) {
+  const int64_t r0 = (int64_t)blockIdx.x * kDotRows;
+  const int64_t r1 = min(r0 + kDotRows, nrows);
+  for (int c = threadIdx.x; c < nrhs; c += kThreads) {
+    double t = 0.0;
+    for (int64_t r = r0; r < r1; ++r) t += (double)A[r * lda + c] * (double)B[r * ldb + c];
+    partial[(int64_t)blockIdx.x * nrhs + c] = t;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce(const double *partial, int64_t nparts,
+                                                     int32_t nrhs, double *out) {
+  __shared__ double s[kThreads];
+  const int c = blockIdx.x;
+  double t = 0.0;
+  for (int64_t w = threadIdx.x; w < nparts; w += kThreads) t += partial[w * nrhs + c];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[c] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int NR>
+hipError_t launch_vec_nr(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
+  if (p.mom)
+    hipLaunchKernelGGL((k_spmm_vec<T, NR, true>), grid, dim3(kThreads), shm, s, p);
+  else
+    hipLaunchKernelGGL((k_spmm_vec<T, NR, false>), grid, dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename T, int NT>
+hipError_t launch_mfma_nt(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
+  if (p.mom)
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, true>), grid, dim3(kThreads), shm, s, p);
+  else
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, false>), grid, dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int NT>
+hipError_t launch_bf16_nt(const FwdParams<float> &p, hipStream_t s, dim3 grid, size_t shm) {
+  if (p.mom)
+    hipLaunchKernelGGL((k_spmm_bf16x3<NT, true>), grid, dim3(kThreads), shm, s, p);
+  else
+    hipLaunchKernelGGL((k_spmm_bf16x3<NT, false>), grid, dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t s) {
+  const int64_t nwg = product_workgroups(p.nrows);
+  if (nwg == 0) return hipSuccess;
+  const dim3 grid((unsigned)nwg);
+  const size_t shm = p.mom ? sizeof(double) * kWaves * (size_t)p.nrhs : 0;
+  if (kind == Kind::Vec) {
+    switch (tile) {
+      case 1: return launch_vec_nr<T, 1>(p, s, grid, shm);
+      case 2: return launch_vec_nr<T, 2>(p, s, grid, shm);
+      case 4: return launch_vec_nr<T, 4>(p, s, grid, shm);
+      default: return launch_vec_nr<T, 8>(p, s, grid, shm);
+    }
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (kind == Kind::Bf16x3) {
+      switch (tile) {
+        case 1: return launch_bf16_nt<1>(p, s, grid, shm);
+        case 2: return launch_bf16_nt<2>(p, s, grid, shm);
+        default: return launch_bf16_nt<4>(p, s, grid, shm);
+      }
+    }
+  }
+  switch (tile) {
+    case 1: return launch_mfma_nt<T, 1>(p, s, grid, shm);
+    case 2: return launch_mfma_nt<T, 2>(p, s, grid, shm);
+    default: return launch_mfma_nt<T, 4>(p, s, grid, shm);
+  }
+}
+
+}  // namespace
+
+int64_t product_workgroups(int64_t nrows) { return (nrows + kWaves - 1) / kWaves; }
+
+hipError_t launch_spmm_f64(const FwdParams<double> &p, Kind kind, int tile, hipStream_t s) {
+  return launch_spmm_t<double>(p, kind == Kind::Bf16x3 ? Kind::Mfma : kind, tile, s);
+}
+hipError_t launch_spmm_f32(const FwdParams<float> &p, Kind kind, int tile, hipStream_t s) {
+  return launch_spmm_t<float>(p, kind, tile, s);
+}
+
+hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void *dst,
+                       int dst_kind, uint16_t *dst_lo, hipStream_t s) {
+  if (p.nnzb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.nnzb + kWaves - 1) / kWaves));
+  hipLaunchKernelGGL(k_pack, grid, dim3(kThreads), 0, s, p, src, src_dtype, dst, dst_kind, dst_lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s) {
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sddmm<double>, dim3((unsigned)product_workgroups(p.n)), dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s) {
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sddmm<float>, dim3((unsigned)product_workgroups(p.n)), dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+int64_t coldot_chunks(int64_t nrows) { return (nrows + kDotRows - 1) / kDotRows; }
+
+hipError_t launch_coldot_f64(const double *A, int64_t lda, const double *B, int64_t ldb,
+                             int64_t nrows, int32_t nrhs, double *partial, int64_t *nchunks,
+                             hipStream_t s) {
+  *nchunks = coldot_chunks(nrows);
+  if (*nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coldot<double>, dim3((unsigned)*nchunks), dim3(kThreads), 0, s, A, lda, B,
+                     ldb, nrows, nrhs, partial);
+  return hipGetLastError();
+}
+hipError_t launch_coldot_f32(const float *A, int64_t lda, const float *B, int64_t ldb,
+                             int64_t nrows, int32_t nrhs, double *partial, int64_t *nchunks,
+                             hipStream_t s) {
+  *nchunks = coldot_chunks(nrows);
+  if (*nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coldot<float>, dim3((unsigned)*nchunks), dim3(kThreads), 0, s, A, lda, B,
+                     ldb, nrows, nrhs, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t nrhs, double *out,
+                                  hipStream_t s) {
+  if (nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce, dim3((unsigned)nrhs), dim3(kThreads), 0, s, partial, nparts, nrhs, out);
+  return hipGetLastError();
+}
+
+}  // namespace vbcsr

@@ -1,0 +1,96 @@
+// Launchers of the gfx950 kernels (implemented in kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+
+namespace vbcsr {
+
+// Arguments of one product launch over all panels of one direction.
+//   Yout[r, c] = alpha * (A X)[r, c] + beta * Yin[r, c]   (Yin unread if beta == 0)
+// With `mom` set, the kernel also adds R[r, c] * Yout[r, c] (in FP64) of its
+// rows into mom[workgroup * nrhs + c].
+template <typename T>
+struct FwdParams {
+  const RowDesc *rows;
+  int32_t nrows;
+  const int32_t *colx;
+  const T *vals;        // FP64/FP32 pages (column-major panels)
+  const uint16_t *hi;   // BF16 pages (8-column groups), BF16X3 only
+  const uint16_t *lo;
+  const int64_t *vbase16;
+  const T *X;
+  int64_t ldx;
+  const T *Yin;
+  int64_t ldyin;
+  T *Yout;
+  int64_t ldy;
+  int32_t nrhs;
+  double alpha, beta;
+  const T *R;           // moment weights (Chebyshev), may be null
+  int64_t ldr;
+  double *mom;          // per-workgroup FP64 partial moments, may be null
+};
+
+// Kernel family and tiling chosen by the router.
+enum class Kind { Vec, Mfma, Bf16x3 };
+
+// Number of workgroups a product launch over `nrows` panels uses (the
+// moment partials have this many rows).
+int64_t product_workgroups(int64_t nrows);
+
+hipError_t launch_spmm_f64(const FwdParams<double> &p, Kind kind, int tile, hipStream_t s);
+hipError_t launch_spmm_f32(const FwdParams<float> &p, Kind kind, int tile, hipStream_t s);
+
+// Graph-order values -> pages of one direction.
+struct PackParams {
+  const int32_t *b;         // per atom
+  const int32_t *blk_row;   // per graph block
+  const int32_t *col_idx;   // per graph block
+  const int64_t *gbase;     // per graph block
+  const int64_t *pos;       // per graph block: page offset of first value
+  const int32_t *k0;        // per graph block: first panel column
+  const int32_t *prow;      // per graph block: panel atom
+  const int64_t *vbase16;   // per atom (BF16 pages)
+  int64_t nnzb;
+  int transposed;           // 0: forward panels, 1: transposed panels
+};
+hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void *dst,
+                       int dst_kind, uint16_t *dst_lo, hipStream_t s);
+// dst_kind: 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages (dst = hi)
+
+// dA (graph order) = block-sampled dY X^T.
+template <typename T>
+struct SddmmParams {
+  const int32_t *b;
+  const int32_t *off;
+  const int64_t *row_ptr;
+  const int32_t *col_idx;
+  const int64_t *gbase;
+  int32_t n;
+  const T *dY;
+  int64_t lddy;
+  const T *X;
+  int64_t ldx;
+  int32_t nrhs;
+  T *dA;
+};
+hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s);
+hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s);
+
+// partial[w * nrhs + c] = sum over rows of chunk w of A[r, c] * B[r, c] (FP64).
+hipError_t launch_coldot_f64(const double *A, int64_t lda, const double *B, int64_t ldb,
+                             int64_t nrows, int32_t nrhs, double *partial, int64_t *nchunks,
+                             hipStream_t s);
+hipError_t launch_coldot_f32(const float *A, int64_t lda, const float *B, int64_t ldb,
+                             int64_t nrows, int32_t nrhs, double *partial, int64_t *nchunks,
+                             hipStream_t s);
+int64_t coldot_chunks(int64_t nrows);
+// out[c] = sum_{w < nparts} partial[w * nrhs + c], fixed order.
+hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t nrhs, double *out,
+                                  hipStream_t s);
+
+}  // namespace vbcsr

@@ -1,0 +1,238 @@
+"""Python front end of the variable-block library (marshalling only).
+
+``Matrix`` wraps one ``vbcsr_mat`` handle.  Every product runs in the HIP
+kernels behind the C ABI; torch supplies device memory and the current
+stream, nothing else.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+_TORCH_DTYPE = {"fp64": torch.float64, "fp32": torch.float32, "bf16x3": torch.float32}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+class Matrix:
+    """A device operator with dense ``b_i x b_j`` blocks (paper, section 2.1).
+
+    ``block_sizes`` [n], ``row_ptr`` [n+1] and ``col_idx`` [nnzb] describe the
+    block graph; ``values`` (graph order, each block row-major) may be a host
+    array, a device tensor or ``None`` (zeros).  ``prec`` is ``"fp64"``,
+    ``"fp32"`` or ``"bf16x3"``.
+    """
+
+    def __init__(self, block_sizes, row_ptr, col_idx, values=None, prec: str = "fp64",
+                 path: str = "auto", nrhs_tile: int = 0):
+        lib = _lib.load()
+        if prec not in _lib.PREC:
+            raise ValueError("prec must be one of %s" % list(_lib.PREC))
+        self.prec = prec
+        self.dtype = _TORCH_DTYPE[prec]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        b = _np(block_sizes, np.int32)
+        rp = _np(row_ptr, np.int64)
+        ci = _np(col_idx, np.int32)
+        self.block_sizes, self.row_ptr, self.col_idx = b, rp, ci
+        self.n = int(b.shape[0])
+        nnz = int((b[np.repeat(np.arange(self.n), np.diff(rp))].astype(np.int64)
+                   * b[ci].astype(np.int64)).sum()) if ci.size else 0
+        self.n_values = nnz
+        self.N = int(b.astype(np.int64).sum())
+        opts = _lib.PlanOpts(0, int(nrhs_tile), _lib.PATH[path])
+        host_vals = None
+        dev_vals = None
+        if isinstance(values, torch.Tensor) and values.is_cuda:
+            dev_vals = values
+        elif values is not None:
+            host_vals = _np(values.cpu().numpy() if isinstance(values, torch.Tensor) else values,
+                            np.float64)
+        h = ctypes.c_void_p()
+        check(lib.vbcsr_create(ctypes.byref(h), self.n, b.ctypes.data, rp.ctypes.data,
+                               ci.ctypes.data if ci.size else None,
+                               host_vals.ctypes.data if host_vals is not None else None,
+                               nnz, _lib.PREC[prec], ctypes.byref(opts), _stream()))
+        self._h = h
+        self._values_key = None
+        if dev_vals is not None:
+            self.set_values(dev_vals)
+
+    @classmethod
+    def from_operator(cls, op, prec="fp64", values=None, **kw):
+        """Build from a ``workloads.Operator``-like object (b, row_ptr, col_idx, values)."""
+        return cls(op.b, op.row_ptr, op.col_idx, op.values if values is None else values,
+                   prec=prec, **kw)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.load().vbcsr_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _vec(self, X, name):
+        if not isinstance(X, torch.Tensor) or not X.is_cuda:
+            raise TypeError("%s must be a CUDA tensor" % name)
+        if X.dtype != self.dtype:
+            raise TypeError("%s must be %s for a %s matrix" % (name, self.dtype, self.prec))
+        if X.dim() == 1:
+            X = X.unsqueeze(1)
+        if X.dim() != 2 or X.shape[0] != self.N:
+            raise ValueError("%s must have %d rows" % (name, self.N))
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        return X
+
+    def info(self):
+        n_rows, nnzb, nval = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        nsh = ctypes.c_int32()
+        check(_lib.load().vbcsr_info(self._h, ctypes.byref(n_rows), ctypes.byref(nnzb),
+                                     ctypes.byref(nval), ctypes.byref(nsh)))
+        return {"N": n_rows.value, "nnzb": nnzb.value, "n_values": nval.value,
+                "n_shapes": nsh.value}
+
+    # -- values -------------------------------------------------------------
+    def set_values(self, values):
+        """Replace all values (graph order); a device tensor is packed by a kernel."""
+        lib = _lib.load()
+        if isinstance(values, torch.Tensor) and values.is_cuda:
+            v = values.detach()
+            if v.dtype not in (torch.float64, torch.float32):
+                raise TypeError("values must be float64 or float32")
+            v = v.contiguous()
+            if v.numel() != self.n_values:
+                raise ValueError("expected %d values" % self.n_values)
+            check(lib.vbcsr_set_values(self._h, _ptr(v), 1, 0 if v.dtype == torch.float64 else 1,
+                                       _stream()))
+            self._values_key = (values.data_ptr(), values._version)
+            self._keepalive = v
+        else:
+            v = _np(values.cpu().numpy() if isinstance(values, torch.Tensor) else values, np.float64)
+            if v.size != self.n_values:
+                raise ValueError("expected %d values" % self.n_values)
+            check(lib.vbcsr_set_values(self._h, v.ctypes.data, 0, 0, _stream()))
+            self._values_key = None
+
+    # -- products -------------------------------------------------------------
+    def spmm(self, X, Y=None, alpha=1.0, beta=0.0, transpose=False):
+        """``Y <- alpha * op(A) X + beta * Y`` with op = identity or transpose."""
+        X = self._vec(X, "X")
+        nrhs = X.shape[1]
+        if Y is None:
+            Y = torch.empty((self.N, nrhs), dtype=self.dtype, device=X.device)
+            beta = 0.0
+        else:
+            if not (isinstance(Y, torch.Tensor) and Y.is_cuda and Y.dtype == self.dtype
+                    and Y.dim() == 2 and Y.shape == (self.N, nrhs) and Y.stride(1) == 1):
+                raise ValueError("Y must be a row-major (N, nrhs) CUDA tensor of the matrix dtype")
+        fn = _lib.load().vbcsr_spmm_t if transpose else _lib.load().vbcsr_spmm
+        check(fn(self._h, _ptr(X), X.stride(0) if self.N else nrhs, _ptr(Y),
+                 Y.stride(0) if self.N else nrhs, nrhs, float(alpha), float(beta), _stream()))
+        return Y
+
+    def spmm_t(self, X, Y=None, alpha=1.0, beta=0.0):
+        return self.spmm(X, Y, alpha, beta, transpose=True)
+
+    def __matmul__(self, X):
+        return self.spmm(X)
+
+    @property
+    def T(self):
+        return _Transposed(self)
+
+    def sddmm(self, dY, X, out=None):
+        """``dA_ij = dY_i X_j^T`` on the stored blocks (graph order)."""
+        dY = self._vec(dY, "dY")
+        X = self._vec(X, "X")
+        if dY.shape[1] != X.shape[1]:
+            raise ValueError("dY and X need the same number of columns")
+        if out is None:
+            out = torch.empty(self.n_values, dtype=self.dtype, device=X.device)
+        check(_lib.load().vbcsr_sddmm(self._h, _ptr(dY), dY.stride(0) if self.N else dY.shape[1],
+                                      _ptr(X), X.stride(0) if self.N else X.shape[1], X.shape[1],
+                                      _ptr(out), _stream()))
+        return out
+
+    def cheb_workspace_bytes(self, nrhs, degree):
+        b = ctypes.c_int64()
+        check(_lib.load().vbcsr_cheb_workspace_bytes(self._h, int(nrhs), int(degree),
+                                                     ctypes.byref(b)))
+        return b.value
+
+    def cheb_moments(self, R, degree: int, workspace=None):
+        """Chebyshev moments ``mu[k, c] = <R_c, T_k(A) R_c>`` (FP64, host array)."""
+        R = self._vec(R, "R")
+        nrhs = R.shape[1]
+        mu = np.empty((degree + 1, nrhs), dtype=np.float64)
+        ws_ptr, ws_bytes = None, 0
+        if workspace is not None:
+            ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+        check(_lib.load().vbcsr_cheb_moments(self._h, _ptr(R), R.stride(0) if self.N else nrhs,
+                                             nrhs, int(degree), mu.ctypes.data, ws_ptr, ws_bytes,
+                                             _stream()))
+        return mu
+
+
+class _Transposed:
+    def __init__(self, A):
+        self.A = A
+
+    def __matmul__(self, X):
+        return self.A.spmm(X, transpose=True)
+
+
+class _SpmmFunction(torch.autograd.Function):
+    """``Y = A(values) X`` with the hand-written backward:
+    ``dX = A^T dY`` (transposed product) and ``dA_ij = dY_i X_j^T`` on the
+    stored blocks (block-sampled product)."""
+
+    @staticmethod
+    def forward(ctx, values, X, A):
+        if A._values_key != (values.data_ptr(), values._version):
+            A.set_values(values)
+        Y = A.spmm(X)
+        ctx.A = A
+        ctx.key = (values.data_ptr(), values._version)
+        ctx.values = values.detach()
+        ctx.save_for_backward(X)
+        return Y
+
+    @staticmethod
+    def backward(ctx, G):
+        (X,) = ctx.saved_tensors
+        A = ctx.A
+        G = G.contiguous()
+        if A._values_key != ctx.key:
+            A.set_values(ctx.values)
+        dV = A.sddmm(G, X) if ctx.needs_input_grad[0] else None
+        dX = A.spmm_t(G) if ctx.needs_input_grad[1] else None
+        if dV is not None and dV.dtype != ctx.values.dtype:
+            dV = dV.to(ctx.values.dtype)
+        return dV, dX, None
+
+
+def spmm(values, X, A: Matrix):
+    """Differentiable ``A(values) @ X`` (values in graph order)."""
+    return _SpmmFunction.apply(values, X, A)

@@ -1,0 +1,193 @@
+"""C-ABI behaviour that needs no GPU: exports, validation, planner maps.
+
+Validation happens on the host before any HIP call, so every error status
+below is produced here on a machine without a device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_04397_amd import _lib
+from workloads import random_pattern, sc_lattice, make_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vbcsr.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vbcsr_\w+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = header_functions()
+    assert len(names) >= 10
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (vbcsr_\w+)", out))
+    assert set(names) <= exported, set(names) - exported
+    assert set(names) == set(_lib.SIGNATURES), "ctypes table and header disagree"
+
+
+def _plan(lib, b, rp, ci, nval, fwd=None, tr=None, max_shapes=256):
+    b = np.ascontiguousarray(b, np.int32)
+    rp = np.ascontiguousarray(rp, np.int64)
+    ci = np.ascontiguousarray(ci, np.int32)
+    ns = ctypes.c_int32()
+    shapes = np.zeros(3 * max_shapes, np.int32)
+    pv = ctypes.c_int64()
+    rc = lib.vbcsr_plan_host(b.size, b.ctypes.data, rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                             nval, ctypes.byref(ns), shapes.ctypes.data, max_shapes,
+                             fwd.ctypes.data if fwd is not None else None,
+                             tr.ctypes.data if tr is not None else None, ctypes.byref(pv))
+    return rc, ns.value, shapes[:3 * ns.value].reshape(-1, 3), pv.value
+
+
+def test_planner_shape_classes_match_recount(lib):
+    op = random_pattern(3, 60, bset=(1, 4, 9, 13), density=0.15, empty_rows=4, unsorted=True)
+    rc, ns, shapes, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz)
+    assert rc == 0
+    bi = op.b[op.block_rows]
+    bj = op.b[op.col_idx]
+    u, c = np.unique(np.stack([bi, bj], 1), axis=0, return_counts=True)
+    assert np.array_equal(shapes[:, :2], u) and np.array_equal(shapes[:, 2], c)
+    assert pv == op.nnz
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_page_maps_are_bijections(lib, seed):
+    op = random_pattern(seed, 50, bset=(1, 2, 5, 9, 13), density=0.2, empty_rows=3, unsorted=True)
+    fwd = np.zeros(op.nnzb, np.int64)
+    tr = np.zeros(op.nnzb, np.int64)
+    rc, _, _, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd, tr)
+    assert rc == 0
+    sizes = op.block_sizes
+    for pos in (fwd, tr):
+        order = np.argsort(pos)
+        starts = pos[order]
+        ends = starts + sizes[order]
+        assert starts[0] == 0 and ends[-1] == pv
+        assert np.array_equal(starts[1:], ends[:-1])  # blocks tile the pages exactly
+
+
+def test_forward_pages_group_rows_and_shapes(lib):
+    """Within the forward pages, the blocks of one block row are contiguous and
+    ordered by (b_j, j); rows follow atom order."""
+    op = random_pattern(11, 40, bset=(1, 4, 9), density=0.3, unsorted=True)
+    fwd = np.zeros(op.nnzb, np.int64)
+    rc, *_ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd)
+    assert rc == 0
+    rows = op.block_rows
+    key = np.lexsort((op.col_idx, op.b[op.col_idx], rows))
+    assert np.all(np.diff(fwd[key]) > 0)
+
+
+def test_transposed_pages_group_columns(lib):
+    op = random_pattern(12, 40, bset=(1, 4, 9), density=0.3, unsorted=True)
+    tr = np.zeros(op.nnzb, np.int64)
+    rc, *_ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, None, tr)
+    assert rc == 0
+    rows = op.block_rows
+    key = np.lexsort((rows, op.b[rows], op.col_idx))
+    assert np.all(np.diff(tr[key]) > 0)
+
+
+def test_uniform_lattice_single_shape(lib):
+    op = sc_lattice(4, 13, seed=2)
+    rc, ns, shapes, _ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz)
+    assert rc == 0 and ns == 1 and tuple(shapes[0]) == (13, 13, 19 * 64)
+
+
+def _case(lib, b, rp, ci, nval):
+    rc, *_ = _plan(lib, b, rp, ci, nval)
+    return rc
+
+
+def test_validation_errors(lib):
+    b = np.array([2, 1, 3], np.int32)
+    rp = np.array([0, 2, 3, 5], np.int64)
+    ci = np.array([0, 2, 1, 0, 2], np.int32)
+    nval = 2 * 2 + 2 * 3 + 1 * 1 + 3 * 2 + 3 * 3
+    assert _case(lib, b, rp, ci, nval) == _lib.VBCSR_OK
+    assert _case(lib, b, rp, ci, nval + 1) == _lib.VBCSR_ESHAPE
+    assert _case(lib, b, np.array([1, 2, 3, 5]), ci, nval) == _lib.VBCSR_EINVAL      # row_ptr[0] != 0
+    assert _case(lib, b, np.array([0, 3, 2, 5]), ci, nval) == _lib.VBCSR_EINVAL      # decreasing
+    assert _case(lib, b, rp, np.array([0, 3, 1, 0, 2]), nval) == _lib.VBCSR_EINVAL   # col out of range
+    assert _case(lib, b, rp, np.array([0, -1, 1, 0, 2]), nval) == _lib.VBCSR_EINVAL
+    assert _case(lib, b, rp, np.array([0, 0, 1, 0, 2]), 2 * 2 * 2 + 1 + 15) == _lib.VBCSR_EDUP
+    assert _case(lib, np.array([2, 0, 3], np.int32), rp, ci, nval) == _lib.VBCSR_EINVAL
+    assert _case(lib, np.array([2, 65, 3], np.int32), rp, ci, nval) == _lib.VBCSR_EUNSUPPORTED
+    msg = lib.vbcsr_last_error().decode()
+    assert "exceeds" in msg
+
+
+def test_empty_graph_is_valid(lib):
+    rc, ns, _, pv = _plan(lib, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32), 0)
+    assert rc == 0 and ns == 0 and pv == 0
+    rc, ns, _, pv = _plan(lib, np.array([3, 4], np.int32), np.zeros(3, np.int64), np.zeros(0, np.int32), 0)
+    assert rc == 0 and ns == 0 and pv == 0
+
+
+def test_null_handle_and_bad_arguments(lib):
+    assert lib.vbcsr_spmm(None, None, 1, None, 1, 1, 1.0, 0.0, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_spmm_t(None, None, 1, None, 1, 1, 1.0, 0.0, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_sddmm(None, None, 1, None, 1, 1, None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_set_values(None, None, 0, 0, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_info(None, None, None, None, None) == _lib.VBCSR_EINVAL
+    lib.vbcsr_destroy(None)
+    h = ctypes.c_void_p()
+    b = np.array([1], np.int32)
+    rp = np.array([0, 1], np.int64)
+    ci = np.array([0], np.int32)
+    assert lib.vbcsr_create(None, 1, b.ctypes.data, rp.ctypes.data, ci.ctypes.data, None, 1, 0,
+                            None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_create(ctypes.byref(h), 1, b.ctypes.data, rp.ctypes.data, ci.ctypes.data,
+                            None, 1, 7, None, None) == _lib.VBCSR_EINVAL
+    opts = _lib.PlanOpts(3, 0, 0)
+    assert lib.vbcsr_create(ctypes.byref(h), 1, b.ctypes.data, rp.ctypes.data, ci.ctypes.data,
+                            None, 1, 0, ctypes.byref(opts), None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_create(ctypes.byref(h), 1, b.ctypes.data, rp.ctypes.data, ci.ctypes.data,
+                            None, 2, 0, None, None) == _lib.VBCSR_ESHAPE
+    assert h.value is None
+
+
+def test_injected_allocation_failure_reports_enomem():
+    """VBCSR_FAIL_ALLOC_AFTER=0 fails the first device allocation before any
+    HIP call, so the out-of-memory path is exercised without a device."""
+    code = r"""
+import ctypes, numpy as np
+from paper_2609_04397_amd import _lib
+lib = _lib.load()
+b = np.array([2, 3], np.int32); rp = np.array([0, 2, 3], np.int64); ci = np.array([0, 1, 1], np.int32)
+h = ctypes.c_void_p()
+rc = lib.vbcsr_create(ctypes.byref(h), 2, b.ctypes.data, rp.ctypes.data, ci.ctypes.data, None,
+                      4 + 6 + 9, 0, None, None)
+print(rc, h.value, lib.vbcsr_last_error().decode())
+"""
+    env = dict(os.environ, VBCSR_FAIL_ALLOC_AFTER="0")
+    out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    rc, hv, msg = out.stdout.split(" ", 2)
+    assert int(rc) == _lib.VBCSR_ENOMEM and hv == "None" and "injected" in msg
+
+
+def test_c3_shape_classes_full_size_small():
+    """The zincblende stand-in has the nine (b_i, b_j) classes of cation (13),
+    anion (9) and passivating (1) atoms."""
+    op, _ = make_config("C3", scale=0.003, nrhs=1)
+    lib = _lib.load()
+    rc, ns, shapes, _ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz)
+    assert rc == 0 and ns == 9
+    assert {(int(a), int(c)) for a, c, _ in shapes} == {(x, y) for x in (1, 9, 13) for y in (1, 9, 13)}

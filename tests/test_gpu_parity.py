@@ -1,0 +1,187 @@
+"""Parity of the HIP products with the FP64 CPU oracle (through the C ABI).
+
+Small inputs span several panels, every block size class the kernels
+distinguish (b = 1, sizes below and above 16, up to 64), empty rows,
+unsorted column order and ragged right-hand-side tiles.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, host, check, rounded, TOL
+from metrics import rel_f, comp
+from workloads import random_pattern, make_config, sc_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+from paper_2609_04397_amd.matrix import Matrix
+
+
+PATTERNS = {
+    "mixed": dict(seed=1, n=40, bset=(1, 4, 9, 13), density=0.2, empty_rows=3, unsorted=True),
+    "wide": dict(seed=2, n=24, bset=(2, 5, 16, 17, 20, 33), density=0.3, empty_rows=1),
+    "big": dict(seed=3, n=10, bset=(64, 31, 48), density=0.5),
+    "scalar": dict(seed=4, n=300, bset=(1,), density=0.03, empty_rows=10, unsorted=True),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(PATTERNS))
+def pattern(request):
+    return request.param, random_pattern(**PATTERNS[request.param])
+
+
+@pytest.mark.parametrize("path,nrhs", [("vec", 1), ("vec", 2), ("vec", 3), ("vec", 8), ("vec", 11),
+                                       ("mfma", 1), ("mfma", 16), ("mfma", 33), ("mfma", 64)])
+def test_fp64_forward_and_transpose(pattern, path, nrhs):
+    name, op = pattern
+    print("case", name, path, nrhs, flush=True)
+    A = Matrix.from_operator(op, prec="fp64", path=path)
+    rng = np.random.default_rng(nrhs)
+    X = rng.standard_normal((op.N, nrhs))
+    Y0 = rng.standard_normal((op.N, nrhs))
+    for transpose in (False, True):
+        ref = (oracle.spmm_t if transpose else oracle.spmm)(op, X, alpha=1.5, beta=-0.5, Y=Y0)
+        Yd = dev(Y0, "fp64")
+        A.spmm(dev(X, "fp64"), Yd, alpha=1.5, beta=-0.5, transpose=transpose)
+        scale = 1.5 * oracle.abs_product(op, X, transpose_op=transpose) + 0.5 * np.abs(Y0)
+        check(host(Yd), ref, "fp64", scale, "%s %s nrhs=%d T=%s" % (name, path, nrhs, transpose))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("nrhs", [1, 8, 16, 40])
+def test_reduced_precision_forward(pattern, prec, nrhs):
+    name, op = pattern
+    print("case", name, prec, nrhs, flush=True)
+    A = Matrix.from_operator(op, prec=prec)
+    X = np.random.default_rng(5).standard_normal((op.N, nrhs))
+    Xr = rounded(X, prec)
+    for transpose in (False, True):
+        ref = (oracle.spmm_t if transpose else oracle.spmm)(op, Xr)
+        got = host(A.spmm(dev(X, prec), transpose=transpose))
+        check(got, ref, prec, label="%s %s nrhs=%d T=%s" % (name, prec, nrhs, transpose))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nrhs", [1, 7, 32])
+def test_sddmm(pattern, prec, nrhs):
+    name, op = pattern
+    print("case sddmm", name, prec, nrhs, flush=True)
+    A = Matrix.from_operator(op, prec=prec)
+    rng = np.random.default_rng(9)
+    dY = rounded(rng.standard_normal((op.N, nrhs)), prec)
+    X = rounded(rng.standard_normal((op.N, nrhs)), prec)
+    ref = oracle.sddmm(op, dY, X)
+    got = host(A.sddmm(dev(dY, prec), dev(X, prec)))
+    scale = oracle.sddmm(op, np.abs(dY), np.abs(X))
+    check(got, ref, prec, scale if prec == "fp64" else None, "sddmm %s %s" % (name, prec))
+
+
+def test_beta_zero_ignores_nan_and_empty_rows():
+    op = random_pattern(7, 30, bset=(3, 9), density=0.2, empty_rows=6)
+    A = Matrix.from_operator(op)
+    X = np.random.default_rng(1).standard_normal((op.N, 4))
+    for path in ("vec", "mfma"):
+        A2 = Matrix.from_operator(op, path=path)
+        Y = torch.full((op.N, 4), float("nan"), dtype=torch.float64, device="cuda")
+        A2.spmm(dev(X, "fp64"), Y, beta=0.0)
+        y = host(Y)
+        assert np.all(np.isfinite(y))
+        check(y, oracle.spmm(op, X), "fp64", oracle.abs_product(op, X))
+    # empty rows: Y_i = beta * Y_i
+    Y0 = np.random.default_rng(2).standard_normal((op.N, 4))
+    Yd = dev(Y0, "fp64")
+    A.spmm(dev(X, "fp64"), Yd, alpha=0.0, beta=2.0)
+    assert np.array_equal(host(Yd), 2.0 * Y0)
+
+
+def test_strided_vectors():
+    op = random_pattern(8, 25, bset=(4, 9), density=0.25)
+    A = Matrix.from_operator(op)
+    Xbig = np.random.default_rng(3).standard_normal((op.N, 10))
+    Xd = dev(Xbig, "fp64")[:, 2:7]          # ld = 10, nrhs = 5
+    Yd = torch.zeros((op.N, 12), dtype=torch.float64, device="cuda")
+    Yv = Yd[:, 1:6]
+    from paper_2609_04397_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _lib.check(lib.vbcsr_spmm(A._h, ctypes.c_void_p(Xd.data_ptr()), 10, ctypes.c_void_p(Yv.data_ptr()),
+                              12, 5, 1.0, 0.0, s))
+    y = host(Yd)
+    check(y[:, 1:6], oracle.spmm(op, Xbig[:, 2:7]), "fp64", oracle.abs_product(op, Xbig[:, 2:7]))
+    assert np.all(y[:, :1] == 0) and np.all(y[:, 6:] == 0)
+
+
+def test_argument_errors_on_device():
+    from paper_2609_04397_amd import _lib, VbcsrError
+    import ctypes
+    op = random_pattern(9, 10, bset=(2, 3), density=0.3)
+    A = Matrix.from_operator(op)
+    lib = _lib.load()
+    X = torch.zeros((op.N, 4), dtype=torch.float64, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = ctypes.c_void_p(X.data_ptr())
+    assert lib.vbcsr_spmm(A._h, p, 4, p, 4, 4, 1.0, 0.0, s) == _lib.VBCSR_EINVAL   # overlap
+    Y = torch.zeros_like(X)
+    q = ctypes.c_void_p(Y.data_ptr())
+    assert lib.vbcsr_spmm(A._h, p, 3, q, 4, 4, 1.0, 0.0, s) == _lib.VBCSR_EINVAL   # ldx < nrhs
+    assert lib.vbcsr_spmm(A._h, p, 4, q, 4, 0, 1.0, 0.0, s) == _lib.VBCSR_EINVAL   # nrhs = 0
+    assert lib.vbcsr_spmm(A._h, None, 4, q, 4, 4, 1.0, 0.0, s) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_sddmm(A._h, p, 4, q, 4, 4, None, s) == _lib.VBCSR_EINVAL
+    with pytest.raises(TypeError):
+        A.spmm(X.float())
+
+
+def test_empty_operator():
+    A = Matrix(np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32))
+    X = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    assert A.spmm(X).shape == (0, 3)
+    assert A.sddmm(X, X).numel() == 0
+    assert A.info()["N"] == 0
+    B = Matrix(np.array([2, 3], np.int32), np.zeros(3, np.int64), np.zeros(0, np.int32))
+    Y0 = torch.ones((5, 2), dtype=torch.float64, device="cuda")
+    B.spmm(torch.ones((5, 2), dtype=torch.float64, device="cuda"), Y0, beta=3.0)
+    assert np.array_equal(host(Y0), np.full((5, 2), 3.0))
+
+
+def test_set_values_host_and_device():
+    op = random_pattern(10, 20, bset=(1, 4, 9), density=0.3)
+    A = Matrix.from_operator(op)
+    X = np.random.default_rng(4).standard_normal((op.N, 3))
+    v2 = np.random.default_rng(5).uniform(-1, 1, op.nnz)
+    A.set_values(v2)
+    check(host(A.spmm(dev(X, "fp64"))), oracle.spmm(op, X, values=v2), "fp64",
+          oracle.abs_product(op, X, values=v2))
+    v3 = np.random.default_rng(6).uniform(-1, 1, op.nnz)
+    A.set_values(dev(v3, "fp64"))
+    check(host(A.spmm(dev(X, "fp64"), transpose=True)), oracle.spmm_t(op, X, values=v3), "fp64",
+          oracle.abs_product(op, X, values=v3, transpose_op=True))
+    # float values into an FP64 handle are widened exactly
+    v4 = v3.astype(np.float32)
+    A.set_values(torch.from_numpy(v4).cuda())
+    check(host(A.spmm(dev(X, "fp64"))), oracle.spmm(op, X, values=v4.astype(np.float64)), "fp64",
+          oracle.abs_product(op, X, values=v4.astype(np.float64)))
+
+
+def test_bitwise_reproducible():
+    op, vec = make_config("C1", scale=0.3, nrhs=16)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        A = Matrix.from_operator(op, prec=prec)
+        X = dev(vec["X"], prec)
+        a = host(A.spmm(X))
+        b = host(A.spmm(X))
+        assert np.array_equal(a, b)
+        assert np.array_equal(host(A.spmm(X, transpose=True)), host(A.spmm(X, transpose=True)))
+        assert np.array_equal(host(A.sddmm(X, X)), host(A.sddmm(X, X)))
+
+
+def test_vec_tiles_agree_with_oracle():
+    op, vec = make_config("C1", scale=0.2, nrhs=8)
+    X = vec["X"]
+    ref = oracle.spmm(op, X)
+    scale = oracle.abs_product(op, X)
+    for tile in (1, 2, 4, 8):
+        A = Matrix.from_operator(op, path="vec", nrhs_tile=tile)
+        check(host(A.spmm(dev(X, "fp64"))), ref, "fp64", scale, "tile %d" % tile)
