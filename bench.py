@@ -1,0 +1,274 @@
+#!/usr/bin/env python
+"""Benchmark of the variable-block sparse hot path on one MI355X.
+
+Workload: the periodic 32x32x32 simple-cubic lattice with 13 orbitals per
+atom (self + 6 + 12 neighbours, 19 blocks per row; 32,768 atoms, N =
+425,984 scalar rows, 622,592 blocks, 105,218,048 values), synthetic seeded
+values, FP64 unless stated.  One *step* is one pass over every product of the
+hot path on this operator:
+
+  spmv_fp64        Y = A x                   nrhs 1   (FP64)
+  spmm_fp64        Y = A X                   nrhs 32  (FP64)
+  spmm_t_fp64      dX = A^T G                nrhs 32  (FP64, adjoint)
+  sddmm_fp64       dA = G X^T on the blocks  nrhs 32  (FP64)
+  cheb_fp64        T <- 2 A' T_k - T, moment nrhs 64  (FP64, A' = A / 1.01||A||_inf)
+  cheb_fp32        the same step, FP32 pages and vectors, FP64 moments
+  cheb_bf16x3      the same step, BF16x3 matrix-core product, FP64 moments
+
+The forward/adjoint/SDDMM triple is the differentiation form (fwd + bwd).
+Timing: W untimed warm-up steps, then K steps bracketed by device
+synchronisation; every call is also bracketed by HIP events on the stream
+it is launched on, which gives each kernel's average duration.
+
+Output: one JSON line (rank 0).  ``value`` is the step's algorithmic HBM
+throughput (sum of algorithmic bytes / step time), ``roofline`` describes the
+kernel with the largest time share, ``cpu_baseline`` times the FP64 CPU
+oracle on a bounded sample of the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def algorithmic_bytes(op, nrhs, s_v, s_x, kind):
+    """Bytes a kernel must move (no padding, each operand once).
+
+    product:   values + 4 B per block index + 8 B per row pointer
+               + X read + Y write (+ Y read when beta != 0)
+    cheb:      product with beta = -1 plus the R read of the fused moment
+    sddmm:     dY and X read + dA written + indices
+    """
+    idx = 4 * op.nnzb + 8 * (op.n + 1)
+    vec = s_x * op.N * nrhs
+    if kind == "product":
+        return s_v * op.nnz + idx + 2 * vec
+    if kind == "cheb":
+        return s_v * op.nnz + idx + 4 * vec
+    if kind == "sddmm":
+        return s_v * op.nnz + idx + 2 * vec
+    raise ValueError(kind)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--lattice", type=int, default=32, help="lattice edge (32 = full workload)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-frac", type=float, default=1.0 / 16,
+                    help="fraction of block rows the CPU oracle processes")
+    ap.add_argument("--only", default="", help="comma list of kernels to run (profiling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
+                 "(requested --gpus %d)" % args.gpus)
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads.core import sc_lattice, inf_norm_scale, scaled
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    t0 = time.time()
+    op = sc_lattice(args.lattice, 13, seed=2, decay=1.0, name="C2")
+    rng = op.meta["_rng"]
+    X32 = rng.standard_normal((op.N, 32))
+    X1 = np.ascontiguousarray(X32[:, :1])
+    G32 = np.random.default_rng(22).standard_normal((op.N, 32))
+    s = inf_norm_scale(op)
+    opc = scaled(op, s, name="C4")
+    R64 = np.random.default_rng(4).standard_normal((op.N, 64))
+    gen_s = time.time() - t0
+
+    t0 = time.time()
+    A64 = Matrix.from_operator(op, prec="fp64")
+    C64 = Matrix.from_operator(opc, prec="fp64")
+    C32 = Matrix.from_operator(opc, prec="fp32")
+    Cbf = Matrix.from_operator(opc, prec="bf16x3")
+    torch.cuda.synchronize()
+    create_s = time.time() - t0
+
+    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float64)
+    d32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
+    x1, x32, g32 = d64(X1), d64(X32), d64(G32)
+    y1 = torch.empty_like(x1)
+    y32 = torch.empty_like(x32)
+    dx32 = torch.empty_like(x32)
+    dA = torch.empty(op.nnz, dtype=torch.float64, device=dev)
+    vecs = {}
+    for name, M, conv in (("fp64", C64, d64), ("fp32", C32, d32), ("bf16x3", Cbf, d32)):
+        R = conv(R64)
+        Tk = conv(np.random.default_rng(5).uniform(-1, 1, (op.N, 64)))
+        Tp = conv(np.random.default_rng(6).uniform(-1, 1, (op.N, 64)))
+        ws = torch.empty(M.cheb_workspace_bytes(64, 0), dtype=torch.uint8, device=dev)
+        mu = torch.zeros(64, dtype=torch.float64, device=dev)
+        vecs[name] = (M, R, Tk, Tp, ws, mu)
+
+    def cheb(name):
+        M, R, Tk, Tp, ws, mu = vecs[name]
+        return lambda: M.cheb_step(Tk, Tp, R, mu, ws)
+
+    kernels = [
+        ("spmv_fp64", lambda: A64.spmm(x1, y1), algorithmic_bytes(op, 1, 8, 8, "product"), 1, "fp64"),
+        ("spmm_fp64", lambda: A64.spmm(x32, y32), algorithmic_bytes(op, 32, 8, 8, "product"), 32, "fp64"),
+        ("spmm_t_fp64", lambda: A64.spmm_t(g32, dx32), algorithmic_bytes(op, 32, 8, 8, "product"), 32, "fp64"),
+        ("sddmm_fp64", lambda: A64.sddmm(g32, x32, dA), algorithmic_bytes(op, 32, 8, 8, "sddmm"), 32, "fp64"),
+        ("cheb_fp64", cheb("fp64"), algorithmic_bytes(op, 64, 8, 8, "cheb"), 64, "fp64"),
+        ("cheb_fp32", cheb("fp32"), algorithmic_bytes(op, 64, 4, 4, "cheb"), 64, "fp32"),
+        ("cheb_bf16x3", cheb("bf16x3"), algorithmic_bytes(op, 64, 4, 4, "cheb"), 64, "bf16"),
+    ]
+    if args.only:
+        keep = set(args.only.split(","))
+        kernels = [k for k in kernels if k[0] in keep]
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        for k in kernels:
+            k[1]()
+    torch.cuda.synchronize()
+
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in kernels] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for st in range(args.steps):
+        for i, k in enumerate(kernels):
+            ev[st][i][0].record(stream)
+            k[1]()
+            ev[st][i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    ms_step = wall * 1e3 / args.steps
+
+    rows = []
+    total_bytes = 0
+    total_flops = 0
+    for i, (name, _, nbytes, nrhs, dt) in enumerate(kernels):
+        times = np.array([ev[st][i][0].elapsed_time(ev[st][i][1]) for st in range(args.steps)])
+        avg_ms = float(times.mean())
+        flops = 2.0 * op.nnz * nrhs
+        total_bytes += nbytes
+        total_flops += flops
+        gbs = nbytes / (avg_ms * 1e-3) / 1e9
+        tf = flops / (avg_ms * 1e-3) / 1e12
+        roof_ms = max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (PEAK_TFLOPS[dt] * 1e12)) * 1e3
+        rows.append({"kernel": name, "nrhs": nrhs, "avg_ms": round(avg_ms, 5),
+                     "median_ms": round(float(np.median(times)), 5),
+                     "min_ms": round(float(times.min()), 5),
+                     "alg_bytes": int(nbytes), "gbs": round(gbs, 1), "tflops": round(tf, 3),
+                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "roofline_frac": round(roof_ms / avg_ms, 4)})
+
+    dom = max(rows, key=lambda r: r["avg_ms"])
+    dom_dt = [k[4] for k in kernels if k[0] == dom["kernel"]][0]
+    hbm_bound = dom["alg_bytes"] / (HBM_PEAK_GBS * 1e9) >= 2.0 * op.nnz * dom["nrhs"] / (PEAK_TFLOPS[dom_dt] * 1e12)
+    if hbm_bound:
+        roof = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4)}
+    else:
+        roof = {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_TFLOPS[dom_dt],
+                "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_TFLOPS[dom_dt], 4)}
+    roof["kernel"] = dom["kernel"]
+    roof["traffic"] = None
+
+    kernel_ms = sum(r["avg_ms"] for r in rows)
+    value = total_bytes / (ms_step * 1e-3) / 1e9
+    fwd = [r for r in rows if r["kernel"] == "spmm_fp64"]
+    fb = [r for r in rows if r["kernel"] in ("spmm_fp64", "spmm_t_fp64", "sddmm_fp64")]
+    out = {
+        "metric": "VBCSR SpMM GFLOP/s & HBM GB/s (% roofline); fwd+bwd ms vs plain FP64",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sc-lattice %d^3, b=13, 19 blocks/row (self+6+12), "
+                               "U[-1,1]*exp(-r) symmetric blocks, X/G/R ~ N(0,1)" % args.lattice,
+                   "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz,
+                   "step": [k[0] for k in kernels]},
+        "gflops": round(total_flops / (ms_step * 1e-3) / 1e9, 1),
+        "kernel_ms_sum": round(kernel_ms, 4),
+        "rows": rows,
+        "roofline": roof,
+        "fwd_bwd_fp64_ms": round(sum(r["avg_ms"] for r in fb), 4) if len(fb) == 3 else None,
+        "fwd_bwd_over_fwd": round(sum(r["avg_ms"] for r in fb) / fwd[0]["avg_ms"], 3)
+        if len(fb) == 3 else None,
+        "setup_s": {"generate": round(gen_s, 2), "create_4_handles": round(create_s, 2)},
+    }
+    if not args.no_cpu and len(kernels) == 7:
+        out["cpu_baseline"] = cpu_baseline(op, opc, X1, X32, G32, R64, total_bytes, args.cpu_frac)
+    print(json.dumps(out))
+
+
+def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, frac):
+    """The FP64 oracle on the first ``frac`` of the block rows of every product
+    of the step (its scalar-CSR expansion and transpose are set-up, excluded
+    like the device planner); the step time is extrapolated by 1/frac."""
+    import oracle
+    from workloads.core import Operator
+
+    nrow_atoms = max(1, int(op.n * frac))
+    nsr = int(op.off[nrow_atoms])
+    rows = np.arange(nsr, dtype=np.int64)
+    A = oracle.expand_op(op)
+    At = oracle.transpose(A)
+    Ac = oracle.expand_op(opc)
+    # sub-operator of the first block rows for the block-sampled product
+    nb = int(op.row_ptr[nrow_atoms])
+    sub = Operator("sub", op.b, np.concatenate([op.row_ptr[:nrow_atoms + 1],
+                                                np.full(op.n - nrow_atoms, nb)]),
+                   op.col_idx[:nb], op.values[:int(op.block_base[nb])], op.dist[:nb])
+    T = np.random.default_rng(5).uniform(-1, 1, (op.N, 64))
+    t = {}
+    t0 = time.perf_counter()
+    oracle.csr_spmm_rows(A, X1, rows)
+    t["spmv_fp64"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.csr_spmm_rows(A, X32, rows)
+    t["spmm_fp64"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.csr_spmm_rows(At, G32, rows)
+    t["spmm_t_fp64"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.sddmm(sub, G32, X32)
+    t["sddmm_fp64"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.csr_spmm_rows(Ac, T, rows)
+    tc = time.perf_counter() - t0
+    for k in ("cheb_fp64", "cheb_fp32", "cheb_bf16x3"):
+        t[k] = tc      # the oracle computes every precision form in FP64
+    f = nsr / op.N
+    est = sum(t.values()) / f
+    return {"value": round(step_bytes / est / 1e9, 3), "unit": "GB/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "first %d of %d block rows (%d scalar rows) of each of the 7 products; "
+                      "FP64 scalar-CSR oracle, measured %.2f s, extrapolated step %.2f s"
+                      % (nrow_atoms, op.n, nsr, sum(t.values()), est),
+            "per_kernel_s": {k: round(v / f, 3) for k, v in t.items()}}
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,24 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
                        void *stream);
 
 /*
+ * vbcsr_cheb_step -- one step of the Chebyshev recurrence of section 5 with
+ * its moment, for callers that drive the recurrence themselves:
+ *   T_next = 2 A T_k - T_prev      (written over T_prev, in place)
+ *   mu_dev[c] = sum_r R[r, c] * T_next[r, c]   (FP64, fixed order)
+ *   Tk         device, N x nrhs, leading dimension ldt >= nrhs, read only
+ *   Tprev      device, N x nrhs, leading dimension ldp >= nrhs; on return it
+ *              holds T_next.  Must not overlap Tk.
+ *   R          device, N x nrhs, leading dimension ldr >= nrhs
+ *   mu_dev     device, nrhs doubles
+ *   workspace  device, >= vbcsr_cheb_workspace_bytes(A, nrhs, 0) bytes
+ * Asynchronous on `stream` (no synchronisation).
+ * Errors: EINVAL, EHIP.
+ */
+int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev, int64_t ldp,
+                    const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
+                    int64_t ws_bytes, void *stream);
+
+/*
  * vbcsr_info -- sizes of a handle: n_rows = N (scalar rows), nnzb stored
  * blocks, n_values = sum of b_i*b_j, n_shapes = distinct (b_i, b_j) classes.
  * Any output pointer may be NULL.

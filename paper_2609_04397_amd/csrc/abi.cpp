@@ -510,6 +510,29 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
   return VBCSR_OK;
 }
 
+int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev, int64_t ldp,
+                    const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
+                    int64_t ws_bytes, void *stream) {
+  int rc = check_vectors(A, Tk, ldt, Tprev, ldp, nrhs, true);
+  if (rc) return rc;
+  if (nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be <= 4096");
+  if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
+  if (!mu_dev) return fail(VBCSR_EINVAL, "mu_dev is NULL");
+  if (A->N == 0) return VBCSR_OK;
+  if (!R) return fail(VBCSR_EINVAL, "R is NULL");
+  int64_t need = 0;
+  if ((rc = vbcsr_cheb_workspace_bytes(A, nrhs, 0, &need))) return rc;
+  if (!workspace || ws_bytes < need) return fail(VBCSR_EINVAL, "workspace missing or too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
+  double *parts = reinterpret_cast<double *>(static_cast<char *>(workspace) + 2 * vec);
+  rc = product(A, 0, Tk, ldt, Tprev, ldp, Tprev, ldp, nrhs, 2.0, -1.0, R, ldr, parts, s);
+  if (rc) return rc;
+  hipError_t e = launch_reduce_partials(parts, product_workgroups(A->n), nrhs, mu_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "moment reduction launch");
+  return VBCSR_OK;
+}
+
 int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
                int32_t *n_shapes) {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");

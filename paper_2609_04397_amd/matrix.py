@@ -38,6 +38,8 @@ class Matrix:
     ``"fp32"`` or ``"bf16x3"``.
     """
 
+    _stamps = 0  # bumped by every value upload; lets autograd detect repacks
+
     def __init__(self, block_sizes, row_ptr, col_idx, values=None, prec: str = "fp64",
                  path: str = "auto", nrhs_tile: int = 0):
         lib = _lib.load()
@@ -69,7 +71,8 @@ class Matrix:
                                host_vals.ctypes.data if host_vals is not None else None,
                                nnz, _lib.PREC[prec], ctypes.byref(opts), _stream()))
         self._h = h
-        self._values_key = None
+        Matrix._stamps += 1
+        self._stamp = Matrix._stamps
         if dev_vals is not None:
             self.set_values(dev_vals)
 
@@ -126,14 +129,14 @@ class Matrix:
                 raise ValueError("expected %d values" % self.n_values)
             check(lib.vbcsr_set_values(self._h, _ptr(v), 1, 0 if v.dtype == torch.float64 else 1,
                                        _stream()))
-            self._values_key = (values.data_ptr(), values._version)
             self._keepalive = v
         else:
             v = _np(values.cpu().numpy() if isinstance(values, torch.Tensor) else values, np.float64)
             if v.size != self.n_values:
                 raise ValueError("expected %d values" % self.n_values)
             check(lib.vbcsr_set_values(self._h, v.ctypes.data, 0, 0, _stream()))
-            self._values_key = None
+        Matrix._stamps += 1
+        self._stamp = Matrix._stamps
 
     # -- products -------------------------------------------------------------
     def spmm(self, X, Y=None, alpha=1.0, beta=0.0, transpose=False):
@@ -195,6 +198,24 @@ class Matrix:
         return mu
 
 
+    def cheb_step(self, Tk, Tprev, R, mu, workspace):
+        """``Tprev <- 2 A Tk - Tprev`` and ``mu[c] = <R_c, Tprev_c>`` (device, FP64)."""
+        Tk = self._vec(Tk, "Tk")
+        nrhs = Tk.shape[1]
+        if not (Tprev.is_cuda and Tprev.dtype == self.dtype and Tprev.shape == Tk.shape
+                and Tprev.stride(1) == 1):
+            raise ValueError("Tprev must match Tk")
+        R = self._vec(R, "R")
+        if mu.dtype != torch.float64 or mu.numel() < nrhs or not mu.is_cuda:
+            raise ValueError("mu must be a CUDA float64 tensor of nrhs entries")
+        check(_lib.load().vbcsr_cheb_step(self._h, _ptr(Tk), Tk.stride(0), _ptr(Tprev),
+                                          Tprev.stride(0), _ptr(R), R.stride(0), nrhs, _ptr(mu),
+                                          _ptr(workspace),
+                                          workspace.numel() * workspace.element_size(),
+                                          _stream()))
+        return Tprev
+
+
 class _Transposed:
     def __init__(self, A):
         self.A = A
@@ -206,30 +227,30 @@ class _Transposed:
 class _SpmmFunction(torch.autograd.Function):
     """``Y = A(values) X`` with the hand-written backward:
     ``dX = A^T dY`` (transposed product) and ``dA_ij = dY_i X_j^T`` on the
-    stored blocks (block-sampled product)."""
+    stored blocks (block-sampled product).  The forward always packs
+    ``values`` into the handle; the backward packs them again only if another
+    forward replaced them in between."""
 
     @staticmethod
     def forward(ctx, values, X, A):
-        if A._values_key != (values.data_ptr(), values._version):
-            A.set_values(values)
+        A.set_values(values)
         Y = A.spmm(X)
         ctx.A = A
-        ctx.key = (values.data_ptr(), values._version)
-        ctx.values = values.detach()
-        ctx.save_for_backward(X)
+        ctx.stamp = A._stamp
+        ctx.save_for_backward(values, X)
         return Y
 
     @staticmethod
     def backward(ctx, G):
-        (X,) = ctx.saved_tensors
+        values, X = ctx.saved_tensors
         A = ctx.A
         G = G.contiguous()
-        if A._values_key != ctx.key:
-            A.set_values(ctx.values)
+        if A._stamp != ctx.stamp:
+            A.set_values(values)
         dV = A.sddmm(G, X) if ctx.needs_input_grad[0] else None
         dX = A.spmm_t(G) if ctx.needs_input_grad[1] else None
-        if dV is not None and dV.dtype != ctx.values.dtype:
-            dV = dV.to(ctx.values.dtype)
+        if dV is not None and dV.dtype != values.dtype:
+            dV = dV.to(values.dtype)
         return dV, dX, None
 
 
