@@ -73,6 +73,7 @@ struct DevDir {
   int64_t *blk_pos = nullptr;
   int32_t *blk_k0 = nullptr;
   int32_t *blk_prow = nullptr;
+  int64_t *colg = nullptr;    // forward direction only
   int64_t n_values = 0, n_values16 = 0;
 };
 
@@ -328,6 +329,7 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_k0, P.blk_k0, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_prow, P.blk_prow, s))) return bail(rc);
+    if (d == 0 && (rc = upload_into(A, &D.colg, P.colg, s))) return bail(rc);
     if (prec == VBCSR_BF16X3) {
       if ((rc = upload_into(A, &D.vbase16, P.vbase16, s))) return bail(rc);
       if ((rc = alloc_into(A, &D.hi, (size_t)P.n_values16))) return bail(rc);
@@ -417,15 +419,14 @@ int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
     return fail(VBCSR_EINVAL, "dA overlaps an input");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t err;
+  const DevDir &D = A->dir[0];
   if (A->prec == VBCSR_FP64) {
-    SddmmParams<double> p{A->b, A->off, A->row_ptr, A->col_idx, A->gbase, A->n,
-                          static_cast<const double *>(dY), lddy, static_cast<const double *>(X),
-                          ldx, nrhs, static_cast<double *>(dA)};
+    SddmmParams<double> p{D.rows, A->n, D.colx, D.colg, static_cast<const double *>(dY), lddy,
+                          static_cast<const double *>(X), ldx, nrhs, static_cast<double *>(dA)};
     err = launch_sddmm_f64(p, s);
   } else {
-    SddmmParams<float> p{A->b, A->off, A->row_ptr, A->col_idx, A->gbase, A->n,
-                         static_cast<const float *>(dY), lddy, static_cast<const float *>(X),
-                         ldx, nrhs, static_cast<float *>(dA)};
+    SddmmParams<float> p{D.rows, A->n, D.colx, D.colg, static_cast<const float *>(dY), lddy,
+                         static_cast<const float *>(X), ldx, nrhs, static_cast<float *>(dA)};
     err = launch_sddmm_f32(p, s);
   }
   if (err != hipSuccess) return hip_fail(err, "sddmm kernel launch");

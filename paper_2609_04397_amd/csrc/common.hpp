@@ -32,6 +32,8 @@ static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 struct DirPlan {
   std::vector<RowDesc> rows;     // one per atom, atom order
   std::vector<int32_t> colx;     // per panel column: scalar row of the input vector
+  std::vector<int64_t> colg;     // forward only, per panel column: (graph offset of the
+                                 // column's block + q) << 7 | b_j (block-sampled product)
   std::vector<int64_t> blk_pos;  // per graph block: page offset of its first value
   std::vector<int32_t> blk_k0;   // per graph block: first panel column
   std::vector<int32_t> blk_prow; // per graph block: atom whose panel holds it

@@ -107,9 +107,15 @@ __device__ __forceinline__ void mom_flush(const double *s_mom, int nrhs, int wg,
 // ---------------------------------------------------------------------------
 // vector-FMA product, NR right-hand sides per pass
 // ---------------------------------------------------------------------------
+// Loads of U consecutive steps are issued before their FMAs, and the panel
+// values and column indices of the next U steps are fetched while the
+// current ones are consumed, so every wave keeps several KB in flight.
+template <typename T, int NR> struct VecUnroll { static constexpr int value = NR <= 2 ? 8 : 4; };
+
 template <typename T, int NR, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
   extern __shared__ double s_mom[];
+  constexpr int U = VecUnroll<T, NR>::value;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -124,6 +130,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
     const int GB = G * b;
     const int nfull = K / G;          // steps in which every group has a column
     const int rem = K - nfull * G;    // groups with a column in the tail step
+    const int nmine = nfull + (g < rem ? 1 : 0);
     const T *__restrict__ v = P.vals + rd.vbase + lane;
     const int32_t *__restrict__ cx = P.colx + rd.cbase + g;
     for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
@@ -133,28 +140,52 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
       for (int c = 0; c < NR; ++c) acc[c] = T(0);
       if (g < G) {
         const T *__restrict__ xb = P.X + c0;
-        if (nc == NR) {
-#pragma unroll 4
-          for (int s = 0; s < nfull; ++s) {
-            const T a = v[(int64_t)s * GB];
-            const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+        int s = 0;
+        if (nc == NR && nfull >= U) {
+          T a[U];
+          int32_t xr[U];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = fma(a, xp[c], acc[c]);
+          for (int u = 0; u < U; ++u) {
+            a[u] = v[(int64_t)u * GB];
+            xr[u] = cx[u * G];
           }
-          if (g < rem) {
-            const T a = v[(int64_t)nfull * GB];
-            const T *xp = xb + (int64_t)cx[nfull * G] * P.ldx;
+          for (; s + U <= nfull; s += U) {
+            T xv[U][NR];
 #pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = fma(a, xp[c], acc[c]);
-          }
-        } else {
-          for (int s = 0; s < nfull + (g < rem ? 1 : 0); ++s) {
-            const T a = v[(int64_t)s * GB];
-            const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+            for (int u = 0; u < U; ++u) {
+              const T *xp = xb + (int64_t)xr[u] * P.ldx;
 #pragma unroll
-            for (int c = 0; c < NR; ++c)
-              if (c < nc) acc[c] = fma(a, xp[c], acc[c]);
+              for (int c = 0; c < NR; ++c) xv[u][c] = xp[c];
+            }
+            T an[U];
+            int32_t xn[U];
+            const bool more = s + 2 * U <= nfull;
+            if (more) {
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                an[u] = v[(int64_t)(s + U + u) * GB];
+                xn[u] = cx[(s + U + u) * G];
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+              for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], xv[u][c], acc[c]);
+            if (more) {
+#pragma unroll
+              for (int u = 0; u < U; ++u) {
+                a[u] = an[u];
+                xr[u] = xn[u];
+              }
+            }
           }
+        }
+        for (; s < nmine; ++s) {
+          const T a = v[(int64_t)s * GB];
+          const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+#pragma unroll
+          for (int c = 0; c < NR; ++c)
+            if (c < nc) acc[c] = fma(a, xp[c], acc[c]);
         }
       }
       // groups g and g + st hold partial sums of the same panel row
@@ -197,16 +228,24 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
 // ---------------------------------------------------------------------------
 // FP64 / FP32 matrix-core product, 16*NT right-hand sides per pass
 // ---------------------------------------------------------------------------
+// A operand: the panel's 4-column slice (contiguous, 4*b values); B operand:
+// the X rows of those 4 columns; U slices are in flight, and the panel values
+// and column indices of the next U slices are prefetched.
+template <typename T, int NT> struct MfmaUnroll {
+  static constexpr int value = (NT * sizeof(T) >= 32) ? 4 : 8;
+};
+
 template <typename T, int NT, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
   extern __shared__ double s_mom[];
   using V = typename Frag<T>::type;
+  constexpr int U = MfmaUnroll<T, NT>::value;
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
   const int m = lane & 15;   // A: panel row in the tile; B and D: column in the tile
-  const int kq = lane >> 4;  // A and B: column of the 4-column slice; D: row quad
+  const int kq = lane >> 4;  // A and B: column of the 4-column slice; D: row group
   mom_init<MOM>(s_mom, P.nrhs);
   if (row < P.nrows) {
     const RowDesc rd = P.rows[row];
@@ -221,17 +260,41 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
         V acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = V{};
-        for (int s = 0; s < nsteps; ++s) {
-          const int k = s * 4 + kq;
-          const bool kin = k < K;
-          const T a = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
-          const int64_t xr = kin ? (int64_t)cx[k] : 0;
-          const T *xp = P.X + xr * P.ldx + c0 + m;
+        T a[U];
+        int32_t xr[U];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const int n = c0 + t * 16 + m;
-            const T x = (kin && n < P.nrhs) ? xp[t * 16] : T(0);
-            acc[t] = mfma(a, x, acc[t]);
+        for (int u = 0; u < U; ++u) {
+          const int k = u * 4 + kq;
+          const bool kin = k < K;
+          a[u] = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
+          xr[u] = kin ? cx[k] : -1;
+        }
+        for (int s = 0; s < nsteps; s += U) {
+          T xv[U][NT];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const T *xp = P.X + (int64_t)xr[u] * P.ldx + c0 + m;
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              xv[u][t] = (xr[u] >= 0 && c0 + t * 16 + m < P.nrhs) ? xp[t * 16] : T(0);
+          }
+          T an[U];
+          int32_t xn[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int k = (s + U + u) * 4 + kq;
+            const bool kin = k < K;
+            an[u] = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
+            xn[u] = kin ? cx[k] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u], xv[u][t], acc[t]);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            a[u] = an[u];
+            xr[u] = xn[u];
           }
         }
 #pragma unroll
@@ -288,35 +351,53 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
         v4f acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = v4f{};
-        for (int s = 0; s < nsteps; ++s) {
+        v8u ah = v8u{}, al = v8u{};
+        int32_t xr[8];
+        auto fetch = [&](int s, v8u &h, v8u &l, int32_t *x) {
           const int grp = s * 4 + kg;
-          v8u ah = v8u{}, al = v8u{};
+          h = v8u{};
+          l = v8u{};
           if (prow && grp < ngroups) {
             const int64_t a = vb16 + (int64_t)grp * 8 * b + p * 8;
-            ah = *reinterpret_cast<const v8u *>(P.hi + a);
-            al = *reinterpret_cast<const v8u *>(P.lo + a);
+            h = *reinterpret_cast<const v8u *>(P.hi + a);
+            l = *reinterpret_cast<const v8u *>(P.lo + a);
           }
-          int64_t xr[8];
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
             const int k = grp * 8 + u;
-            xr[u] = k < K ? (int64_t)cx[k] : -1;
+            x[u] = k < K ? cx[k] : -1;
           }
+        };
+        fetch(0, ah, al, xr);
+        for (int s = 0; s < nsteps; ++s) {
+          float xv[NT][8];
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             const int n = c0 + t * 16 + m;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+              xv[t][u] = (xr[u] >= 0 && n < P.nrhs) ? P.X[(int64_t)xr[u] * P.ldx + n] : 0.0f;
+          }
+          v8u nh, nl;
+          int32_t xn[8];
+          fetch(s + 1, nh, nl, xn);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
             v8u xh, xl;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-              const float xv = (xr[u] >= 0 && n < P.nrhs) ? P.X[xr[u] * P.ldx + n] : 0.0f;
-              const unsigned short h = bf16_rne(xv);
+              const unsigned short h = bf16_rne(xv[t][u]);
               xh[u] = h;
-              xl[u] = bf16_rne(xv - bf16_to_f32(h));
+              xl[u] = bf16_rne(xv[t][u] - bf16_to_f32(h));
             }
             acc[t] = mfma_bf16(ah, xh, acc[t]);
             acc[t] = mfma_bf16(ah, xl, acc[t]);
             acc[t] = mfma_bf16(al, xh, acc[t]);
           }
+          ah = nh;
+          al = nl;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xr[u] = xn[u];
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -384,27 +465,67 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
 }
 
 // ---------------------------------------------------------------------------
-// block-sampled dY X^T, one wave per block row, graph-order output
+// block-sampled dY X^T on matrix cores, one wave per forward panel
 // ---------------------------------------------------------------------------
+// For block row i the result is the b_i x K_i panel dY_i Xg_i^T, Xg_i the X
+// rows of the panel's columns: a 16 x 16 output tile per MFMA chain with
+// M = panel rows, N = 16 panel columns, K = right-hand sides.  Lane (m, kq)
+// holds right-hand sides 8kq..8kq+7 of each 32-wide chunk contiguously for
+// both operands (the contraction order inside a chunk is permuted, the sum is
+// the same).  Each output goes to graph order through colg = (graph offset of
+// the column's block + q) << 7 | b_j.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_sddmm(SddmmParams<T> P) {
-  const int i = xcd_remap(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-  if (i >= P.n) return;
+__global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
+  using V = typename Frag<T>::type;
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+  if (row >= P.nrows) return;
   const int lane = threadIdx.x & 63;
-  const int bi = P.b[i];
-  const int64_t yoff = P.off[i];
-  for (int64_t k = P.row_ptr[i]; k < P.row_ptr[i + 1]; ++k) {
-    const int j = P.col_idx[k];
-    const int bj = P.b[j];
-    const int64_t xoff = P.off[j];
-    const int64_t base = P.gbase[k];
-    for (int e = lane; e < bi * bj; e += 64) {
-      const int p = e / bj, q = e - p * bj;
-      const T *dy = P.dY + (yoff + p) * P.lddy;
-      const T *x = P.X + (xoff + q) * P.ldx;
-      T acc = T(0);
-      for (int c = 0; c < P.nrhs; ++c) acc = fma(dy[c], x[c], acc);
-      P.dA[base + e] = acc;
+  const int m = lane & 15;
+  const int kq = lane >> 4;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  const int nch = (P.nrhs + 31) >> 5;
+  const int32_t *__restrict__ cx = P.colx + rd.cbase;
+  const int64_t *__restrict__ cg = P.colg + rd.cbase;
+  for (int mt = 0; mt * 16 < b; ++mt) {
+    const int p = mt * 16 + m;
+    const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : 0)) * P.lddy;
+    // A fragments of the first two chunks stay in registers for the whole row
+    T af[2][8];
+#pragma unroll
+    for (int ch = 0; ch < 2; ++ch)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int c = ch * 32 + kq * 8 + s;
+        af[ch][s] = (p < b && c < P.nrhs) ? dyrow[c] : T(0);
+      }
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      const int kc = k0 + m;
+      const bool kin = kc < K;
+      const T *xrow = P.X + (kin ? (int64_t)cx[kc] : 0) * P.ldx;
+      V acc = V{};
+      for (int ch = 0; ch < nch; ++ch) {
+        T bv[8], av[8] = {};
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int c = ch * 32 + kq * 8 + s;
+          bv[s] = (kin && c < P.nrhs) ? xrow[c] : T(0);
+          if (ch >= 2) av[s] = (p < b && c < P.nrhs) ? dyrow[c] : T(0);
+        }
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          acc = mfma(ch == 0 ? af[0][s] : ch == 1 ? af[1][s] : av[s], bv[s], acc);
+      }
+      if (kin) {
+        const int64_t g = cg[kc];
+        const int64_t base = g >> 7;
+        const int bj = (int)(g & 127);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pr = mt * 16 + dst_row<T>(kq, i);
+          if (pr < b) P.dA[base + (int64_t)pr * bj] = acc[i];
+        }
+      }
     }
   }
 }
@@ -521,13 +642,15 @@ hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void
 }
 
 hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s) {
-  if (p.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sddmm<double>, dim3((unsigned)product_workgroups(p.n)), dim3(kThreads), 0, s, p);
+  if (p.nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sddmm_mfma<double>, dim3((unsigned)product_workgroups(p.nrows)),
+                     dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
 hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s) {
-  if (p.n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sddmm<float>, dim3((unsigned)product_workgroups(p.n)), dim3(kThreads), 0, s, p);
+  if (p.nrows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sddmm_mfma<float>, dim3((unsigned)product_workgroups(p.nrows)),
+                     dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
 

@@ -62,15 +62,13 @@ hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void
                        int dst_kind, uint16_t *dst_lo, hipStream_t s);
 // dst_kind: 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages (dst = hi)
 
-// dA (graph order) = block-sampled dY X^T.
+// dA (graph order) = block-sampled dY X^T, over the forward panels.
 template <typename T>
 struct SddmmParams {
-  const int32_t *b;
-  const int32_t *off;
-  const int64_t *row_ptr;
-  const int32_t *col_idx;
-  const int64_t *gbase;
-  int32_t n;
+  const RowDesc *rows;   // forward panels
+  int32_t nrows;
+  const int32_t *colx;   // per panel column: X row
+  const int64_t *colg;   // per panel column: (graph offset of block + q) << 7 | b_j
   const T *dY;
   int64_t lddy;
   const T *X;

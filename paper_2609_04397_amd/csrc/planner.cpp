@@ -61,7 +61,12 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 // together with the atom that indexes their panel columns.
 static void layout_direction(int32_t n, const int32_t *b, const std::vector<int64_t> &off,
                              const std::vector<std::vector<std::pair<int32_t, int64_t>>> &members,
-                             int64_t nnzb, DirPlan &d) {
+                             int64_t nnzb, const std::vector<int64_t> *gbase, DirPlan &d) {
+  int64_t total_cols = 0;
+  for (int32_t r = 0; r < n; ++r)
+    for (const auto &m : members[r]) total_cols += b[m.first];
+  d.colx.reserve(total_cols);
+  if (gbase) d.colg.reserve(total_cols);
   d.rows.resize(n);
   d.vbase16.resize(n);
   d.blk_pos.assign(nnzb, 0);
@@ -87,7 +92,10 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
       d.blk_pos[k] = vbase + (int64_t)k0 * h;
       d.blk_k0[k] = k0;
       d.blk_prow[k] = r;
-      for (int32_t q = 0; q < b[c]; ++q) d.colx.push_back((int32_t)(off[c] + q));
+      for (int32_t q = 0; q < b[c]; ++q) {
+        d.colx.push_back((int32_t)(off[c] + q));
+        if (gbase) d.colg.push_back((((*gbase)[k] + q) << 7) | b[c]);
+      }
       k0 += b[c];
     }
     vbase += (int64_t)h * K;
@@ -132,7 +140,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
       return x.first < y.first;
     });
   }
-  layout_direction(n, b, plan.off, members, nnzb, plan.fwd);
+  layout_direction(n, b, plan.off, members, nnzb, &plan.gbase, plan.fwd);
 
   // transposed: panel j holds the blocks (i, j) of block column j, ordered by (b_i, i)
   for (auto &m : members) m.clear();
@@ -144,7 +152,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
       if (b[x.first] != b[y.first]) return b[x.first] < b[y.first];
       return x.first < y.first;
     });
-  layout_direction(n, b, plan.off, members, nnzb, plan.tr);
+  layout_direction(n, b, plan.off, members, nnzb, nullptr, plan.tr);
 }
 
 }  // namespace vbcsr
