@@ -22,8 +22,12 @@ ARCH = "gfx950"
 
 SOURCES = ["kernels.hip", "abi.cpp", "planner.cpp"]
 
-# Packed FP32 instructions are disabled for every device compile.
-DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# Packed FP32 instructions are disabled for every device compile.  Matrix-core
+# accumulators are kept in ordinary VGPRs: with AGPR accumulators the compiler
+# copies every FP64 accumulator tile between the two register files around
+# each MFMA inside loops (about 16 extra VALU instructions per MFMA).
+DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def hipcc() -> str:

@@ -104,22 +104,41 @@ __device__ __forceinline__ void mom_flush(const double *s_mom, int nrhs, int wg,
   }
 }
 
+// Wave-private LDS hand-off (LDS writes of a wave become visible to its
+// own later LDS reads; no workgroup barrier needed).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Panel values are read exactly once per product: stream them past the
+// caches (non-temporal) so the gathered X rows stay resident.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
 // ---------------------------------------------------------------------------
 // vector-FMA product, NR right-hand sides per pass
 // ---------------------------------------------------------------------------
-// Loads of U consecutive steps are issued before their FMAs, and the panel
-// values and column indices of the next U steps are fetched while the
-// current ones are consumed, so every wave keeps several KB in flight.
-template <typename T, int NR> struct VecUnroll { static constexpr int value = NR <= 2 ? 8 : 4; };
+// The X rows of a chunk of panel columns are first gathered into a
+// wave-private LDS buffer, so the value stream never waits on a dependent
+// index -> X load chain.  The values of the next U steps are in flight while
+// the current U steps are multiplied.
+constexpr int kXsBytes = 4096;  // LDS staging per wave
 
 template <typename T, int NR, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
   extern __shared__ double s_mom[];
-  constexpr int U = VecUnroll<T, NR>::value;
+  constexpr int XCAP = kXsBytes / sizeof(T);
+  constexpr int U = NR <= 2 ? 4 : 2;
+  __shared__ T xs_all[kWaves * XCAP];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
+  T *xs = xs_all + w * XCAP;
   mom_init<MOM>(s_mom, P.nrhs);
   if (row < P.nrows) {
     const RowDesc rd = P.rows[row];
@@ -128,64 +147,60 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
     const int g = lane / b;
     const int p = lane - g * b;
     const int GB = G * b;
-    const int nfull = K / G;          // steps in which every group has a column
-    const int rem = K - nfull * G;    // groups with a column in the tail step
-    const int nmine = nfull + (g < rem ? 1 : 0);
-    const T *__restrict__ v = P.vals + rd.vbase + lane;
-    const int32_t *__restrict__ cx = P.colx + rd.cbase + g;
+    const int ccap = (XCAP / NR) / G * G;  // panel columns per staged chunk
+    const T *__restrict__ vrow = P.vals + rd.vbase + lane;
+    const int32_t *__restrict__ cxrow = P.colx + rd.cbase;
     for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
       const int nc = min(NR, P.nrhs - c0);
       T acc[NR];
 #pragma unroll
       for (int c = 0; c < NR; ++c) acc[c] = T(0);
-      if (g < G) {
-        const T *__restrict__ xb = P.X + c0;
+      for (int kc = 0; kc < K; kc += ccap) {
+        const int kn = min(ccap, K - kc);
+        const int nfull = kn / G;
+        const int nmine = nfull + (g < kn - nfull * G ? 1 : 0);
+        const T *__restrict__ v = vrow + (int64_t)kc * b;
+        // the first value loads go out before the gather
+        T a[U];
+        const bool piped = g < G && nfull >= U;
+        if (piped) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) a[u] = stream_load(v + (int64_t)u * GB);
+        }
+        wave_lds_sync();  // previous chunk fully consumed
+        for (int e = lane; e < kn * NR; e += 64) {
+          const int col = e / NR, c = e - col * NR;
+          xs[e] = c < nc ? P.X[(int64_t)cxrow[kc + col] * P.ldx + c0 + c] : T(0);
+        }
+        wave_lds_sync();
         int s = 0;
-        if (nc == NR && nfull >= U) {
-          T a[U];
-          int32_t xr[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            a[u] = v[(int64_t)u * GB];
-            xr[u] = cx[u * G];
-          }
+        if (piped) {
           for (; s + U <= nfull; s += U) {
-            T xv[U][NR];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const T *xp = xb + (int64_t)xr[u] * P.ldx;
-#pragma unroll
-              for (int c = 0; c < NR; ++c) xv[u][c] = xp[c];
-            }
             T an[U];
-            int32_t xn[U];
             const bool more = s + 2 * U <= nfull;
             if (more) {
 #pragma unroll
-              for (int u = 0; u < U; ++u) {
-                an[u] = v[(int64_t)(s + U + u) * GB];
-                xn[u] = cx[(s + U + u) * G];
-              }
+              for (int u = 0; u < U; ++u) an[u] = stream_load(v + (int64_t)(s + U + u) * GB);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; ++u) {
+              const T *xp = xs + ((s + u) * G + g) * NR;
 #pragma unroll
-              for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], xv[u][c], acc[c]);
+              for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], xp[c], acc[c]);
+            }
             if (more) {
 #pragma unroll
-              for (int u = 0; u < U; ++u) {
-                a[u] = an[u];
-                xr[u] = xn[u];
-              }
+              for (int u = 0; u < U; ++u) a[u] = an[u];
             }
           }
         }
-        for (; s < nmine; ++s) {
-          const T a = v[(int64_t)s * GB];
-          const T *xp = xb + (int64_t)cx[s * G] * P.ldx;
+        if (g < G) {
+          for (; s < nmine; ++s) {
+            const T av = stream_load(v + (int64_t)s * GB);
+            const T *xp = xs + (s * G + g) * NR;
 #pragma unroll
-          for (int c = 0; c < NR; ++c)
-            if (c < nc) acc[c] = fma(a, xp[c], acc[c]);
+            for (int c = 0; c < NR; ++c) acc[c] = fma(av, xp[c], acc[c]);
+          }
         }
       }
       // groups g and g + st hold partial sums of the same panel row
@@ -226,20 +241,33 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32 matrix-core product, 16*NT right-hand sides per pass
+// FP64 / FP32 matrix-core product
 // ---------------------------------------------------------------------------
-// A operand: the panel's 4-column slice (contiguous, 4*b values); B operand:
-// the X rows of those 4 columns; U slices are in flight, and the panel values
-// and column indices of the next U slices are prefetched.
-template <typename T, int NT> struct MfmaUnroll {
-  static constexpr int value = (NT * sizeof(T) >= 32) ? 4 : 8;
-};
+// A operand: the panel's 4-column slice (contiguous, 4*b values, panel row m
+// in lane m, slice column kq in lane group kq); B operand: the X rows of
+// those 4 columns.  The values and column indices of the next U slices are
+// in flight while the current U slices multiply.
+//
+// Fast path (VX = true): the N index of the 16x16 tiles is permuted so that
+// lane m of tile t holds right-hand side c0 + l*16*VEC + VEC*m + e, with
+// t = l*VEC + e and VEC elements per 16 bytes: one 16-byte load per lane and
+// X row fetches VEC tiles, and outputs are written back 16 bytes at a time.
+// It needs 16-byte aligned vectors, leading dimensions that are multiples of
+// VEC and nrhs a multiple of 16*VEC*L.  The generic path (VX = false) loads
+// one element per lane and tile and handles any nrhs and leading dimension.
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
 
-template <typename T, int NT, bool MOM>
+template <typename T, int NT, bool MOM, bool VX>
 __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
   extern __shared__ double s_mom[];
   using V = typename Frag<T>::type;
-  constexpr int U = MfmaUnroll<T, NT>::value;
+  using L16 = typename Vec16<T>::type;
+  constexpr int VEC = Vec16<T>::n;
+  constexpr int NL = VX ? NT / VEC : 0;  // 16-byte loads per lane and X row
+  constexpr int U = 4;
+  static_assert(!VX || NT % VEC == 0, "tile count must fill whole 16-byte loads");
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -253,6 +281,10 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
     const int nsteps = (K + 3) >> 2;
     const T *__restrict__ vals = P.vals + rd.vbase;
     const int32_t *__restrict__ cx = P.colx + rd.cbase;
+    // column of (tile t, lane m) relative to c0
+    auto col = [&](int t) {
+      return VX ? (t / VEC) * 16 * VEC + VEC * m + (t % VEC) : t * 16 + m;
+    };
     for (int mt = 0; mt * 16 < b; ++mt) {
       const int p = mt * 16 + m;
       const bool prow = p < b;
@@ -266,17 +298,28 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
         for (int u = 0; u < U; ++u) {
           const int k = u * 4 + kq;
           const bool kin = k < K;
-          a[u] = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
+          a[u] = (kin && prow) ? stream_load(vals + (int64_t)k * b + p) : T(0);
           xr[u] = kin ? cx[k] : -1;
         }
         for (int s = 0; s < nsteps; s += U) {
           T xv[U][NT];
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const T *xp = P.X + (int64_t)xr[u] * P.ldx + c0 + m;
+            const T *xp = P.X + (int64_t)xr[u] * P.ldx + c0;
+            if constexpr (VX) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-              xv[u][t] = (xr[u] >= 0 && c0 + t * 16 + m < P.nrhs) ? xp[t * 16] : T(0);
+              for (int l = 0; l < (VX ? NL : 1); ++l) {
+                L16 q = xr[u] >= 0 ? *reinterpret_cast<const L16 *>(xp + l * 16 * VEC + VEC * m)
+                                   : L16{};
+                const T *qe = reinterpret_cast<const T *>(&q);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) xv[u][l * VEC + e] = qe[e];
+              }
+            } else {
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                xv[u][t] = (xr[u] >= 0 && c0 + t * 16 + m < P.nrhs) ? xp[t * 16 + m] : T(0);
+            }
           }
           T an[U];
           int32_t xn[U];
@@ -284,7 +327,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
           for (int u = 0; u < U; ++u) {
             const int k = (s + U + u) * 4 + kq;
             const bool kin = k < K;
-            an[u] = (kin && prow) ? vals[(int64_t)k * b + p] : T(0);
+            an[u] = (kin && prow) ? stream_load(vals + (int64_t)k * b + p) : T(0);
             xn[u] = kin ? cx[k] : -1;
           }
 #pragma unroll
@@ -297,24 +340,60 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
             xr[u] = xn[u];
           }
         }
+        // epilogue: row pr of the tile, columns col(t)
+        double mmv[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int n = c0 + t * 16 + m;
-          double mm = 0.0;
+        for (int t = 0; t < NT; ++t) mmv[t] = 0.0;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int pr = mt * 16 + dst_row<T>(kq, i);
-            if (pr < b && n < P.nrhs) {
-              const int64_t r = (int64_t)rd.yrow + pr;
-              T y = T(P.alpha) * acc[t][i];
-              if (P.beta != 0.0) y = fma(T(P.beta), P.Yin[r * P.ldyin + n], y);
-              P.Yout[r * P.ldy + n] = y;
-              if (MOM) mm += (double)P.R[r * P.ldr + n] * (double)y;
+        for (int i = 0; i < 4; ++i) {
+          const int pr = mt * 16 + dst_row<T>(kq, i);
+          if (pr < b) {
+            const int64_t r = (int64_t)rd.yrow + pr;
+            T y[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) y[t] = T(P.alpha) * acc[t][i];
+            if constexpr (VX) {
+#pragma unroll
+              for (int l = 0; l < (VX ? NL : 1); ++l) {
+                const int64_t cc = c0 + l * 16 * VEC + VEC * m;
+                if (P.beta != 0.0) {
+                  const L16 q = *reinterpret_cast<const L16 *>(P.Yin + r * P.ldyin + cc);
+                  const T *qe = reinterpret_cast<const T *>(&q);
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) y[l * VEC + e] = fma(T(P.beta), qe[e], y[l * VEC + e]);
+                }
+                L16 o;
+                T *oe = reinterpret_cast<T *>(&o);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e) oe[e] = y[l * VEC + e];
+                *reinterpret_cast<L16 *>(P.Yout + r * P.ldy + cc) = o;
+                if (MOM) {
+                  const L16 q = *reinterpret_cast<const L16 *>(P.R + r * P.ldr + cc);
+                  const T *qe = reinterpret_cast<const T *>(&q);
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) mmv[l * VEC + e] += (double)qe[e] * (double)oe[e];
+                }
+              }
+            } else {
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                const int n = c0 + t * 16 + m;
+                if (n < P.nrhs) {
+                  if (P.beta != 0.0) y[t] = fma(T(P.beta), P.Yin[r * P.ldyin + n], y[t]);
+                  P.Yout[r * P.ldy + n] = y[t];
+                  if (MOM) mmv[t] += (double)P.R[r * P.ldr + n] * (double)y[t];
+                }
+              }
             }
           }
-          if (MOM) {
+        }
+        if (MOM) {
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            double mm = mmv[t];
             mm += __shfl_xor(mm, 16, 64);
             mm += __shfl_xor(mm, 32, 64);
+            const int n = c0 + col(t);
             if (kq == 0 && n < P.nrhs) s_mom[w * P.nrhs + n] += mm;
           }
         }
@@ -327,6 +406,11 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
 // ---------------------------------------------------------------------------
 // BF16x3 matrix-core product: a*x ~ ah*xh + ah*xl + al*xh, FP32 accumulation
 // ---------------------------------------------------------------------------
+// 32-column slices; lane (m, kg) owns 8 consecutive panel columns of row m
+// (one 16-byte load per page) and, for the B operand, the same 8 columns of
+// X in column m of the tile.  X is split into bf16 hi/lo on the fly.  Loads
+// are branch-free and the next slice's values and indices are in flight
+// while the current slice multiplies.
 template <int NT, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
   extern __shared__ double s_mom[];
@@ -347,40 +431,48 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
     for (int mt = 0; mt * 16 < b; ++mt) {
       const int p = mt * 16 + m;
       const bool prow = p < b;
+      const int pc = prow ? p : b - 1;
       for (int c0 = 0; c0 < P.nrhs; c0 += 16 * NT) {
+        int nn[NT];
+        bool nok[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int n = c0 + t * 16 + m;
+          nok[t] = n < P.nrhs;
+          nn[t] = nok[t] ? n : P.nrhs - 1;
+        }
         v4f acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = v4f{};
-        v8u ah = v8u{}, al = v8u{};
-        int32_t xr[8];
         auto fetch = [&](int s, v8u &h, v8u &l, int32_t *x) {
           const int grp = s * 4 + kg;
-          h = v8u{};
-          l = v8u{};
-          if (prow && grp < ngroups) {
-            const int64_t a = vb16 + (int64_t)grp * 8 * b + p * 8;
-            h = *reinterpret_cast<const v8u *>(P.hi + a);
-            l = *reinterpret_cast<const v8u *>(P.lo + a);
-          }
+          const bool ok = prow && grp < ngroups;
+          const int64_t a = vb16 + (int64_t)min(grp, max(ngroups - 1, 0)) * 8 * b + pc * 8;
+          const v8u hv = stream_load(reinterpret_cast<const v8u *>(P.hi + a));
+          const v8u lv = stream_load(reinterpret_cast<const v8u *>(P.lo + a));
+          h = ok ? hv : v8u{};
+          l = ok ? lv : v8u{};
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int k = grp * 8 + u;
-            x[u] = k < K ? cx[k] : -1;
-          }
+          for (int u = 0; u < 8; ++u) x[u] = cx[min(grp * 8 + u, K - 1)];
         };
-        fetch(0, ah, al, xr);
+        v8u ah, al;
+        int32_t xr[8];
+        if (K > 0) fetch(0, ah, al, xr);
         for (int s = 0; s < nsteps; ++s) {
           float xv[NT][8];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) {
-            const int n = c0 + t * 16 + m;
+          for (int u = 0; u < 8; ++u) {
+            const bool kin = (s * 4 + kg) * 8 + u < K;
+            const float *xp = P.X + (int64_t)xr[u] * P.ldx;
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-              xv[t][u] = (xr[u] >= 0 && n < P.nrhs) ? P.X[(int64_t)xr[u] * P.ldx + n] : 0.0f;
+            for (int t = 0; t < NT; ++t) {
+              const float v = xp[nn[t]];
+              xv[t][u] = (kin && nok[t]) ? v : 0.0f;
+            }
           }
           v8u nh, nl;
           int32_t xn[8];
-          fetch(s + 1, nh, nl, xn);
+          fetch(min(s + 1, nsteps - 1), nh, nl, xn);
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             v8u xh, xl;
@@ -489,7 +581,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   const int64_t *__restrict__ cg = P.colg + rd.cbase;
   for (int mt = 0; mt * 16 < b; ++mt) {
     const int p = mt * 16 + m;
-    const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : 0)) * P.lddy;
+    const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
     // A fragments of the first two chunks stay in registers for the whole row
     T af[2][8];
 #pragma unroll
@@ -497,20 +589,41 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
         const int c = ch * 32 + kq * 8 + s;
-        af[ch][s] = (p < b && c < P.nrhs) ? dyrow[c] : T(0);
+        const T v = dyrow[min(c, P.nrhs - 1)];
+        af[ch][s] = (p < b && c < P.nrhs) ? v : T(0);
       }
     for (int k0 = 0; k0 < K; k0 += 16) {
       const int kc = k0 + m;
       const bool kin = kc < K;
-      const T *xrow = P.X + (kin ? (int64_t)cx[kc] : 0) * P.ldx;
+      const T *xrow = P.X + (int64_t)cx[min(kc, K - 1)] * P.ldx;
       V acc = V{};
       for (int ch = 0; ch < nch; ++ch) {
         T bv[8], av[8] = {};
+        const int cb = ch * 32 + kq * 8;
+        if (cb + 8 <= P.nrhs) {
+          // whole 8-wide run inside the row: contiguous vector loads
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-          const int c = ch * 32 + kq * 8 + s;
-          bv[s] = (kin && c < P.nrhs) ? xrow[c] : T(0);
-          if (ch >= 2) av[s] = (p < b && c < P.nrhs) ? dyrow[c] : T(0);
+          for (int s = 0; s < 8; ++s) bv[s] = xrow[cb + s];
+#pragma unroll
+          for (int s = 0; s < 8; ++s) bv[s] = kin ? bv[s] : T(0);
+          if (ch >= 2) {
+#pragma unroll
+            for (int s = 0; s < 8; ++s) av[s] = dyrow[cb + s];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) av[s] = p < b ? av[s] : T(0);
+          }
+        } else {
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            const int c = cb + s;
+            const int cc = min(c, P.nrhs - 1);
+            const T xv = xrow[cc];
+            bv[s] = (kin && c < P.nrhs) ? xv : T(0);
+            if (ch >= 2) {
+              const T dv = dyrow[cc];
+              av[s] = (p < b && c < P.nrhs) ? dv : T(0);
+            }
+          }
         }
 #pragma unroll
         for (int s = 0; s < 8; ++s)
@@ -574,13 +687,27 @@ hipError_t launch_vec_nr(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t
   return hipGetLastError();
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool VX>
 hipError_t launch_mfma_nt(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
   if (p.mom)
-    hipLaunchKernelGGL((k_spmm_mfma<T, NT, true>), grid, dim3(kThreads), shm, s, p);
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, true, VX>), grid, dim3(kThreads), shm, s, p);
   else
-    hipLaunchKernelGGL((k_spmm_mfma<T, NT, false>), grid, dim3(kThreads), 0, s, p);
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, false, VX>), grid, dim3(kThreads), 0, s, p);
   return hipGetLastError();
+}
+
+// The vectorised fast path applies when every vector is 16-byte aligned,
+// every leading dimension is a multiple of the 16-byte element count and the
+// right-hand sides fill whole passes.
+template <typename T>
+bool vectorizable(const FwdParams<T> &p, int nt) {
+  constexpr int VEC = 16 / sizeof(T);
+  auto al = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  if (p.nrhs % (16 * nt) != 0) return false;
+  if (!al(p.X) || !al(p.Yout) || (p.beta != 0.0 && !al(p.Yin)) || (p.mom && !al(p.R))) return false;
+  if (p.ldx % VEC || p.ldy % VEC || (p.beta != 0.0 && p.ldyin % VEC) || (p.mom && p.ldr % VEC))
+    return false;
+  return true;
 }
 
 template <int NT>
@@ -615,10 +742,18 @@ hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t
       }
     }
   }
+  // matrix cores: tile = right-hand-side tiles of 16 per pass
+  constexpr int VEC = 16 / sizeof(T);
+  if (tile >= VEC && vectorizable(p, tile)) {
+    if constexpr (VEC == 2) {
+      if (tile == 2) return launch_mfma_nt<T, 2, true>(p, s, grid, shm);
+    }
+    return launch_mfma_nt<T, 4, true>(p, s, grid, shm);
+  }
   switch (tile) {
-    case 1: return launch_mfma_nt<T, 1>(p, s, grid, shm);
-    case 2: return launch_mfma_nt<T, 2>(p, s, grid, shm);
-    default: return launch_mfma_nt<T, 4>(p, s, grid, shm);
+    case 1: return launch_mfma_nt<T, 1, false>(p, s, grid, shm);
+    case 2: return launch_mfma_nt<T, 2, false>(p, s, grid, shm);
+    default: return launch_mfma_nt<T, 4, false>(p, s, grid, shm);
   }
 }
 
