@@ -518,6 +518,132 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
   mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
 }
 
+// BF16x3 fast path: 64 right-hand sides per pass, tile t of lane m holds
+// column c0 + 4m + t, so the 8 X rows of a lane's 8-column group arrive as
+// eight 16-byte loads; each row splits into hi/lo with the hardware
+// round-to-nearest-even conversion (two values per instruction).
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned int pack_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned int, v2bf{(__bf16)a, (__bf16)b});
+}
+
+template <bool MOM>
+__global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P) {
+  extern __shared__ double s_mom[];
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = wg * kWaves + w;
+  const int m = lane & 15;
+  const int kg = lane >> 4;
+  mom_init<MOM>(s_mom, P.nrhs);
+  if (row < P.nrows) {
+    const RowDesc rd = P.rows[row];
+    const int b = rd.b, K = rd.K;
+    const int ngroups = (K + 7) >> 3;
+    const int nsteps = (K + 31) >> 5;
+    const int64_t vb16 = P.vbase16[row];
+    const int32_t *__restrict__ cx = P.colx + rd.cbase;
+    for (int mt = 0; mt * 16 < b; ++mt) {
+      const int p = mt * 16 + m;
+      const bool prow = p < b;
+      for (int c0 = 0; c0 < P.nrhs; c0 += 64) {
+        v4f acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = v4f{};
+        auto fetch = [&](int s, v8u &h, v8u &l, int32_t *x) {
+          const int grp = s * 4 + kg;
+          const bool ok = prow && grp < ngroups;
+          h = v8u{};
+          l = v8u{};
+          if (ok) {
+            const int64_t a = vb16 + (int64_t)grp * 8 * b + p * 8;
+            h = stream_load(reinterpret_cast<const v8u *>(P.hi + a));
+            l = stream_load(reinterpret_cast<const v8u *>(P.lo + a));
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int k = grp * 8 + u;
+            x[u] = k < K ? cx[k] : -1;
+          }
+        };
+        v8u ah, al;
+        int32_t xr[8];
+        fetch(0, ah, al, xr);
+        for (int s = 0; s < nsteps; ++s) {
+          float4 xv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            xv[u] = xr[u] >= 0
+                        ? *reinterpret_cast<const float4 *>(P.X + (int64_t)xr[u] * P.ldx + c0 + 4 * m)
+                        : float4{0.f, 0.f, 0.f, 0.f};
+          v8u nh, nl;
+          int32_t xn[8];
+          fetch(s + 1, nh, nl, xn);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            v4u hi, lo;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float x0 = reinterpret_cast<const float *>(&xv[2 * q])[t];
+              const float x1 = reinterpret_cast<const float *>(&xv[2 * q + 1])[t];
+              const unsigned int h = pack_bf16(x0, x1);
+              hi[q] = h;
+              lo[q] = pack_bf16(x0 - __uint_as_float(h << 16), x1 - __uint_as_float(h & 0xFFFF0000u));
+            }
+            const v8u xh = __builtin_bit_cast(v8u, hi), xl = __builtin_bit_cast(v8u, lo);
+            acc[t] = mfma_bf16(ah, xh, acc[t]);
+            acc[t] = mfma_bf16(ah, xl, acc[t]);
+            acc[t] = mfma_bf16(al, xh, acc[t]);
+          }
+          ah = nh;
+          al = nl;
+#pragma unroll
+          for (int u = 0; u < 8; ++u) xr[u] = xn[u];
+        }
+        double mmv[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pr = mt * 16 + dst_row<float>(kg, i);
+          if (pr < b) {
+            const int64_t r = (int64_t)rd.yrow + pr;
+            const int64_t cc = c0 + 4 * m;
+            float4 y = {float(P.alpha) * acc[0][i], float(P.alpha) * acc[1][i],
+                        float(P.alpha) * acc[2][i], float(P.alpha) * acc[3][i]};
+            if (P.beta != 0.0) {
+              const float4 q = *reinterpret_cast<const float4 *>(P.Yin + r * P.ldyin + cc);
+              const float be = float(P.beta);
+              y.x = fmaf(be, q.x, y.x);
+              y.y = fmaf(be, q.y, y.y);
+              y.z = fmaf(be, q.z, y.z);
+              y.w = fmaf(be, q.w, y.w);
+            }
+            *reinterpret_cast<float4 *>(P.Yout + r * P.ldy + cc) = y;
+            if (MOM) {
+              const float4 q = *reinterpret_cast<const float4 *>(P.R + r * P.ldr + cc);
+              mmv[0] += (double)q.x * (double)y.x;
+              mmv[1] += (double)q.y * (double)y.y;
+              mmv[2] += (double)q.z * (double)y.z;
+              mmv[3] += (double)q.w * (double)y.w;
+            }
+          }
+        }
+        if (MOM) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            double mm = mmv[t];
+            mm += __shfl_xor(mm, 16, 64);
+            mm += __shfl_xor(mm, 32, 64);
+            if (kg == 0) s_mom[w * P.nrhs + c0 + 4 * m + t] += mm;
+          }
+        }
+      }
+    }
+  }
+  mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
+}
+
 // ---------------------------------------------------------------------------
 // value packing: graph order (row-major blocks) -> pages
 // ---------------------------------------------------------------------------
@@ -576,68 +702,84 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   const int kq = lane >> 4;
   const RowDesc rd = P.rows[row];
   const int b = rd.b, K = rd.K;
+  if (K == 0) return;
   const int nch = (P.nrhs + 31) >> 5;
+  const int ntiles = (K + 15) >> 4;
   const int32_t *__restrict__ cx = P.colx + rd.cbase;
   const int64_t *__restrict__ cg = P.colg + rd.cbase;
   for (int mt = 0; mt * 16 < b; ++mt) {
     const int p = mt * 16 + m;
     const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
-    // A fragments of the first two chunks stay in registers for the whole row
+    auto ldrun = [&](const T *src, int cb, bool ok, T *dst) {
+      // 8 consecutive right-hand sides starting at cb (zero outside)
+      if (cb + 8 <= P.nrhs) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) dst[s] = src[cb + s];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) dst[s] = ok ? dst[s] : T(0);
+      } else {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int c = cb + s;
+          const T v = src[min(c, P.nrhs - 1)];
+          dst[s] = (ok && c < P.nrhs) ? v : T(0);
+        }
+      }
+    };
+    // A fragments (dY rows) of the first two 32-wide chunks stay in registers
     T af[2][8];
 #pragma unroll
-    for (int ch = 0; ch < 2; ++ch)
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        const int c = ch * 32 + kq * 8 + s;
-        const T v = dyrow[min(c, P.nrhs - 1)];
-        af[ch][s] = (p < b && c < P.nrhs) ? v : T(0);
-      }
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      const int kc = k0 + m;
-      const bool kin = kc < K;
-      const T *xrow = P.X + (int64_t)cx[min(kc, K - 1)] * P.ldx;
+    for (int ch = 0; ch < 2; ++ch) ldrun(dyrow, ch * 32 + kq * 8, p < b && ch < nch, af[ch]);
+    // one 16-column tile: B fragments of chunk 0/1 and the output map
+    struct Tile {
+      T bv[2][8];
+      const T *xrow;
+      int64_t g;
+      bool kin;
+    };
+    auto load_tile = [&](int j, Tile &tl) {
+      const int kc = j * 16 + m;
+      tl.kin = kc < K;
+      const int kk = tl.kin ? kc : K - 1;
+      tl.xrow = P.X + (int64_t)cx[kk] * P.ldx;
+      tl.g = cg[kk];
+      ldrun(tl.xrow, kq * 8, tl.kin, tl.bv[0]);
+      if (nch > 1) ldrun(tl.xrow, 32 + kq * 8, tl.kin, tl.bv[1]);
+    };
+    auto do_tile = [&](const Tile &tl) {
       V acc = V{};
-      for (int ch = 0; ch < nch; ++ch) {
-        T bv[8], av[8] = {};
-        const int cb = ch * 32 + kq * 8;
-        if (cb + 8 <= P.nrhs) {
-          // whole 8-wide run inside the row: contiguous vector loads
 #pragma unroll
-          for (int s = 0; s < 8; ++s) bv[s] = xrow[cb + s];
+      for (int s = 0; s < 8; ++s) acc = mfma(af[0][s], tl.bv[0][s], acc);
+      if (nch > 1) {
 #pragma unroll
-          for (int s = 0; s < 8; ++s) bv[s] = kin ? bv[s] : T(0);
-          if (ch >= 2) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s) av[s] = dyrow[cb + s];
-#pragma unroll
-            for (int s = 0; s < 8; ++s) av[s] = p < b ? av[s] : T(0);
-          }
-        } else {
-#pragma unroll
-          for (int s = 0; s < 8; ++s) {
-            const int c = cb + s;
-            const int cc = min(c, P.nrhs - 1);
-            const T xv = xrow[cc];
-            bv[s] = (kin && c < P.nrhs) ? xv : T(0);
-            if (ch >= 2) {
-              const T dv = dyrow[cc];
-              av[s] = (p < b && c < P.nrhs) ? dv : T(0);
-            }
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < 8; ++s)
-          acc = mfma(ch == 0 ? af[0][s] : ch == 1 ? af[1][s] : av[s], bv[s], acc);
+        for (int s = 0; s < 8; ++s) acc = mfma(af[1][s], tl.bv[1][s], acc);
       }
-      if (kin) {
-        const int64_t g = cg[kc];
-        const int64_t base = g >> 7;
-        const int bj = (int)(g & 127);
+      for (int ch = 2; ch < nch; ++ch) {
+        T av[8], bv[8];
+        ldrun(dyrow, ch * 32 + kq * 8, p < b, av);
+        ldrun(tl.xrow, ch * 32 + kq * 8, tl.kin, bv);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) acc = mfma(av[s], bv[s], acc);
+      }
+      if (tl.kin) {
+        const int64_t base = tl.g >> 7;
+        const int bj = (int)(tl.g & 127);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int pr = mt * 16 + dst_row<T>(kq, i);
           if (pr < b) P.dA[base + (int64_t)pr * bj] = acc[i];
         }
+      }
+    };
+    // ping-pong: the next tile's operands load while the current one multiplies
+    Tile t0, t1;
+    load_tile(0, t0);
+    for (int j = 0; j < ntiles; j += 2) {
+      if (j + 1 < ntiles) load_tile(j + 1, t1);
+      do_tile(t0);
+      if (j + 1 < ntiles) {
+        if (j + 2 < ntiles) load_tile(j + 2, t0);
+        do_tile(t1);
       }
     }
   }
@@ -735,6 +877,13 @@ hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t
   }
   if constexpr (std::is_same<T, float>::value) {
     if (kind == Kind::Bf16x3) {
+      if (vectorizable(p, 4)) {
+        if (p.mom)
+          hipLaunchKernelGGL((k_spmm_bf16x3_vx<true>), grid, dim3(kThreads), shm, s, p);
+        else
+          hipLaunchKernelGGL((k_spmm_bf16x3_vx<false>), grid, dim3(kThreads), 0, s, p);
+        return hipGetLastError();
+      }
       switch (tile) {
         case 1: return launch_bf16_nt<1>(p, s, grid, shm);
         case 2: return launch_bf16_nt<2>(p, s, grid, shm);
