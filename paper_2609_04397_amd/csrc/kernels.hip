@@ -119,6 +119,56 @@ __device__ __forceinline__ T stream_load(const T *p) {
   return __builtin_nontemporal_load(p);
 }
 
+// Gather the X rows of panel columns [kc, kc + kn) into a wave-private LDS
+// tile xs[col * NRP + c] (NRP >= nc values per row, zero-padded).  Each lane
+// owns whole columns: the column indices of up to CPL columns per lane are
+// loaded first, then every X load, then the LDS writes, so a chunk costs two
+// memory round trips however many columns it holds.
+template <typename T, int NRP, int CPL>
+__device__ __forceinline__ void stage_x(T *xs, const int32_t *__restrict__ cx, const T *__restrict__ X,
+                                        int64_t ldx, int c0, int nc, int kc, int kn, int lane) {
+  for (int k0 = 0; k0 < kn; k0 += 64 * CPL) {
+    int32_t xr[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int k = k0 + j * 64 + lane;
+      xr[j] = k < kn ? cx[kc + k] : -1;
+    }
+    T v[CPL][NRP];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const T *xp = X + (int64_t)(xr[j] >= 0 ? xr[j] : 0) * ldx + c0;
+#pragma unroll
+      for (int c = 0; c < NRP; ++c) v[j][c] = (xr[j] >= 0 && c < nc) ? xp[c] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int k = k0 + j * 64 + lane;
+      if (k < kn) {
+#pragma unroll
+        for (int c = 0; c < NRP; ++c) xs[k * NRP + c] = v[j][c];
+      }
+    }
+  }
+}
+
+// Raw buffer access to one panel: the descriptor (base, size in bytes) is
+// wave-uniform and lives in scalar registers, each lane supplies a 32-bit
+// byte offset, and offsets at or beyond the size read as zero.  Panel value
+// streams use the non-temporal hint.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t panel_rsrc(const void *base, uint32_t bytes) {
+  // 0x00020000: raw 32-bit buffer format of the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T> __device__ __forceinline__ T buf_load_nt(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buf_load_nt<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2));
+}
+template <> __device__ __forceinline__ float buf_load_nt<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+
 // ---------------------------------------------------------------------------
 // vector-FMA product, NR right-hand sides per pass
 // ---------------------------------------------------------------------------
@@ -143,12 +193,17 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
   if (row < P.nrows) {
     const RowDesc rd = P.rows[row];
     const int b = rd.b, K = rd.K;
-    const int G = 64 / b;
+    // G column groups of b lanes; capped so that one staged chunk holds at
+    // least G*U columns of NR values (otherwise ccap below would be 0 and the
+    // chunk loop would not advance: b = 1 gives 64 groups)
+    constexpr int GMAX = XCAP / (NR * U);
+    static_assert(GMAX >= 1, "LDS staging buffer too small");
+    const int G = min(64 / b, GMAX);
     const int g = lane / b;
     const int p = lane - g * b;
     const int GB = G * b;
-    const int ccap = (XCAP / NR) / G * G;  // panel columns per staged chunk
-    const T *__restrict__ vrow = P.vals + rd.vbase + lane;
+    // panel columns per staged chunk: a positive multiple of G*U that fits
+    const int ccap = (XCAP / NR) / (G * U) * (G * U);
     const int32_t *__restrict__ cxrow = P.colx + rd.cbase;
     for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
       const int nc = min(NR, P.nrhs - c0);
@@ -157,49 +212,34 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
       for (int c = 0; c < NR; ++c) acc[c] = T(0);
       for (int kc = 0; kc < K; kc += ccap) {
         const int kn = min(ccap, K - kc);
-        const int nfull = kn / G;
-        const int nmine = nfull + (g < kn - nfull * G ? 1 : 0);
-        const T *__restrict__ v = vrow + (int64_t)kc * b;
-        // the first value loads go out before the gather
+        // steps over the chunk, rounded up to whole groups of U; values past
+        // the chunk read as zero and meet zero-padded staged X rows
+        const int ngrp = (kn + G * U - 1) / (G * U);
+        const __amdgpu_buffer_rsrc_t vr =
+            panel_rsrc(P.vals + rd.vbase + (int64_t)kc * b, (uint32_t)(kn * b * sizeof(T)));
+        const uint32_t lo = (uint32_t)lane * sizeof(T);
+        const uint32_t stepb = (uint32_t)GB * sizeof(T);
         T a[U];
-        const bool piped = g < G && nfull >= U;
-        if (piped) {
 #pragma unroll
-          for (int u = 0; u < U; ++u) a[u] = stream_load(v + (int64_t)u * GB);
-        }
+        for (int u = 0; u < U; ++u) a[u] = buf_load_nt<T>(vr, lo + u * stepb);
         wave_lds_sync();  // previous chunk fully consumed
-        for (int e = lane; e < kn * NR; e += 64) {
-          const int col = e / NR, c = e - col * NR;
-          xs[e] = c < nc ? P.X[(int64_t)cxrow[kc + col] * P.ldx + c0 + c] : T(0);
-        }
+        stage_x<T, NR, (NR <= 2 ? 4 : 2)>(xs, cxrow, P.X, P.ldx, c0, nc, kc, kn, lane);
+        for (int e = kn * NR + lane; e < ngrp * G * U * NR; e += 64) xs[e] = T(0);
         wave_lds_sync();
-        int s = 0;
-        if (piped) {
-          for (; s + U <= nfull; s += U) {
+        if (g < G) {
+          for (int q = 0; q < ngrp; ++q) {
+            const int s = q * U;
             T an[U];
-            const bool more = s + 2 * U <= nfull;
-            if (more) {
 #pragma unroll
-              for (int u = 0; u < U; ++u) an[u] = stream_load(v + (int64_t)(s + U + u) * GB);
-            }
+            for (int u = 0; u < U; ++u) an[u] = buf_load_nt<T>(vr, lo + (s + U + u) * stepb);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
               const T *xp = xs + ((s + u) * G + g) * NR;
 #pragma unroll
               for (int c = 0; c < NR; ++c) acc[c] = fma(a[u], xp[c], acc[c]);
             }
-            if (more) {
 #pragma unroll
-              for (int u = 0; u < U; ++u) a[u] = an[u];
-            }
-          }
-        }
-        if (g < G) {
-          for (; s < nmine; ++s) {
-            const T av = stream_load(v + (int64_t)s * GB);
-            const T *xp = xs + (s * G + g) * NR;
-#pragma unroll
-            for (int c = 0; c < NR; ++c) acc[c] = fma(av, xp[c], acc[c]);
+            for (int u = 0; u < U; ++u) a[u] = an[u];
           }
         }
       }

@@ -1,0 +1,186 @@
+"""Full-size parity at the configurations the benchmark uses.
+
+The oracle cannot afford every row of the largest operators, so it computes
+sampled rows exactly: the operator restricted to the sampled block rows (or,
+for the adjoint, to the sampled block columns) gives the same sums for those
+rows as the full operator.  Small configurations are checked in full.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import dev, host, check, rounded
+from metrics import rel_f, comp
+from workloads import make_config
+from workloads.core import Operator
+
+pytestmark = pytest.mark.gpu
+
+from paper_2609_04397_amd.matrix import Matrix
+
+
+def restrict(op, keep_blocks):
+    """Same atoms, only the blocks with keep_blocks[k] (graph order kept)."""
+    keep = np.asarray(keep_blocks, dtype=bool)
+    rows = op.block_rows
+    base = op.block_base
+    sizes = np.diff(base)
+    counts = np.bincount(rows[keep], minlength=op.n)
+    rp = np.zeros(op.n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    vmask = np.repeat(keep, sizes)
+    return Operator(op.name + "-sub", op.b, rp, op.col_idx[keep], op.values[vmask], op.dist[keep])
+
+
+def sample_atoms(op, k, seed):
+    rng = np.random.default_rng(seed)
+    atoms = np.unique(np.concatenate([[0, op.n - 1], rng.choice(op.n, size=min(k, op.n), replace=False)]))
+    off = op.off
+    srows = np.concatenate([np.arange(off[a], off[a + 1]) for a in atoms])
+    return atoms, srows
+
+
+def check_forward_rows(op, A, X, prec, atoms, srows, label):
+    sub = restrict(op, np.isin(op.block_rows, atoms))
+    Xr = rounded(X, prec)
+    got = host(A.spmm(dev(X, prec)))[srows]
+    ref = oracle.spmm(sub, Xr)[srows]
+    scale = oracle.abs_product(sub, Xr)[srows]
+    return check(got, ref, prec, scale if prec == "fp64" else None, label)
+
+
+def check_adjoint_rows(op, A, X, prec, atoms, srows, label):
+    sub = restrict(op, np.isin(op.col_idx, atoms))
+    Xr = rounded(X, prec)
+    got = host(A.spmm_t(dev(X, prec)))[srows]
+    ref = oracle.spmm_t(sub, Xr)[srows]
+    scale = oracle.abs_product(sub, Xr, transpose_op=True)[srows]
+    return check(got, ref, prec, scale if prec == "fp64" else None, label)
+
+
+def check_sddmm_blocks(op, A, dY, X, prec, atoms, label):
+    keep = np.isin(op.block_rows, atoms)
+    sub = restrict(op, keep)
+    dYr, Xr = rounded(dY, prec), rounded(X, prec)
+    got = host(A.sddmm(dev(dY, prec), dev(X, prec)))
+    vmask = np.repeat(keep, np.diff(op.block_base))
+    ref = oracle.sddmm(sub, dYr, Xr)
+    scale = oracle.sddmm(sub, np.abs(dYr), np.abs(Xr))
+    return check(got[vmask], ref, prec, scale if prec == "fp64" else None, label)
+
+
+def test_c1_full():
+    op, vec = make_config("C1")
+    X = vec["X"]
+    A = Matrix.from_operator(op)
+    for nrhs in (1, 2, 4, 8, 16):
+        Xn = np.ascontiguousarray(X[:, :nrhs])
+        print("case C1 nrhs", nrhs, flush=True)
+        r = check(host(A.spmm(dev(Xn, "fp64"))), oracle.spmm(op, Xn), "fp64",
+                  oracle.abs_product(op, Xn), "C1 fwd %d" % nrhs)
+        print("C1 nrhs %d rel_F %.2e" % (nrhs, r))
+    check(host(A.spmm_t(dev(X, "fp64"))), oracle.spmm_t(op, X), "fp64",
+          oracle.abs_product(op, X, transpose_op=True), "C1 adjoint")
+    G = np.random.default_rng(11).standard_normal(X.shape)
+    check(host(A.sddmm(dev(G, "fp64"), dev(X, "fp64"))), oracle.sddmm(op, G, X), "fp64",
+          oracle.sddmm(op, np.abs(G), np.abs(X)), "C1 sddmm")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    op, _ = make_config("C2", nrhs=1)
+    rng = np.random.default_rng(21)
+    return op, rng.standard_normal((op.N, 32)), rng.standard_normal((op.N, 32))
+
+
+@pytest.mark.timeout(300)
+def test_c2_fp64_sampled(c2):
+    op, X32, G32 = c2
+    atoms, srows = sample_atoms(op, 1500, 1)
+    A = Matrix.from_operator(op)
+    for nrhs in (1, 2, 4, 8, 32):
+        print("case C2 fwd nrhs", nrhs, flush=True)
+        Xn = np.ascontiguousarray(X32[:, :nrhs])
+        r = check_forward_rows(op, A, Xn, "fp64", atoms, srows, "C2 fwd %d" % nrhs)
+        print("C2 nrhs %d rel_F %.2e" % (nrhs, r))
+    print("case C2 adjoint", flush=True)
+    check_adjoint_rows(op, A, G32, "fp64", atoms, srows, "C2 adjoint 32")
+    print("case C2 sddmm", flush=True)
+    check_sddmm_blocks(op, A, G32, X32, "fp64", atoms, "C2 sddmm 32")
+
+
+@pytest.mark.timeout(300)
+def test_c4_precision_forms_sampled(c2):
+    op, _, _ = c2
+    op4, vec = make_config("C4", nrhs=64)
+    R = vec["R"]
+    atoms, srows = sample_atoms(op4, 800, 2)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        print("case C4", prec, flush=True)
+        A = Matrix.from_operator(op4, prec=prec)
+        # the product the recurrence applies, on the full operator, sampled rows
+        r = check_forward_rows(op4, A, R, prec, atoms, srows, "C4 %s" % prec)
+        # headline error against the FP64 oracle on the FP64 inputs
+        sub = restrict(op4, np.isin(op4.block_rows, atoms))
+        got = host(A.spmm(dev(R, prec)))[srows]
+        r64 = rel_f(got, oracle.spmm(sub, R)[srows])
+        print("C4 %s rel_F %.3e (vs FP64 inputs %.3e)" % (prec, r, r64))
+        A.close()
+
+
+@pytest.mark.timeout(400)
+def test_c4_moments_full_size_low_degree(c2):
+    op4, vec = make_config("C4", nrhs=64)
+    R = vec["R"]
+    deg = 3
+    ref = oracle.cheb_moments(op4, R, deg)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5), ("bf16x3", 5e-5)):
+        A = Matrix.from_operator(op4, prec=prec)
+        mu = A.cheb_moments(dev(R, prec), deg)
+        err = np.max(np.abs(mu - ref)) / np.max(np.abs(ref[0]))
+        print("C4 moments %s degree %d err %.3e" % (prec, deg, err))
+        assert err <= tol
+        A.close()
+
+
+@pytest.mark.timeout(300)
+def test_c5_fwd_bwd_fp32_sampled():
+    op, vec = make_config("C5")
+    X, G = vec["X"], vec["G"]
+    vals32 = op.values.astype(np.float32).astype(np.float64)
+    op32 = Operator(op.name, op.b, op.row_ptr, op.col_idx, vals32, op.dist)
+    A = Matrix.from_operator(op, prec="fp32")
+    atoms, srows = sample_atoms(op, 1500, 3)
+    print("case C5 fwd", flush=True)
+    check_forward_rows(op32, A, X, "fp32", atoms, srows, "C5 fwd")
+    print("case C5 adjoint", flush=True)
+    check_adjoint_rows(op32, A, G, "fp32", atoms, srows, "C5 adjoint")
+    print("case C5 sddmm", flush=True)
+    check_sddmm_blocks(op32, A, G, X, "fp32", atoms, "C5 sddmm")
+    A.close()
+    A64 = Matrix.from_operator(op, prec="fp64")
+    check_forward_rows(op, A64, X, "fp64", atoms, srows, "C5 fwd fp64")
+    check_adjoint_rows(op, A64, G, "fp64", atoms, srows, "C5 adjoint fp64")
+    check_sddmm_blocks(op, A64, G, X, "fp64", atoms, "C5 sddmm fp64")
+
+
+@pytest.mark.timeout(600)
+def test_c3_zincblende_sampled():
+    op, _ = make_config("C3", nrhs=1)
+    rng = np.random.default_rng(31)
+    X = rng.standard_normal((op.N, 64))
+    atoms, srows = sample_atoms(op, 1200, 4)
+    # include passivating atoms and their hosts explicitly
+    h = np.nonzero(op.b == 1)[0][:50]
+    atoms = np.unique(np.concatenate([atoms, h]))
+    off = op.off
+    srows = np.concatenate([np.arange(off[a], off[a + 1]) for a in atoms])
+    A = Matrix.from_operator(op)
+    for nrhs in (1, 8, 64):
+        print("case C3 nrhs", nrhs, flush=True)
+        Xn = np.ascontiguousarray(X[:, :nrhs])
+        r = check_forward_rows(op, A, Xn, "fp64", atoms, srows, "C3 fwd %d" % nrhs)
+        print("C3 nrhs %d rel_F %.2e" % (nrhs, r))
+    check_adjoint_rows(op, A, np.ascontiguousarray(X[:, :8]), "fp64", atoms, srows, "C3 adjoint 8")
+    A.close()
