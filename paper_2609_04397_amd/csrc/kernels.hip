@@ -732,7 +732,7 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
 // both operands (the contraction order inside a chunk is permuted, the sum is
 // the same).  Each output goes to graph order through colg = (graph offset of
 // the column's block + q) << 7 | b_j.
-template <typename T>
+template <typename T, int NCH>
 __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   using V = typename Frag<T>::type;
   const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
@@ -766,13 +766,13 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
         }
       }
     };
-    // A fragments (dY rows) of the first two 32-wide chunks stay in registers
-    T af[2][8];
+    // A fragments (dY rows) of the first NCH 32-wide chunks stay in registers
+    T af[NCH][8];
 #pragma unroll
-    for (int ch = 0; ch < 2; ++ch) ldrun(dyrow, ch * 32 + kq * 8, p < b && ch < nch, af[ch]);
+    for (int ch = 0; ch < NCH; ++ch) ldrun(dyrow, ch * 32 + kq * 8, p < b && ch < nch, af[ch]);
     // one 16-column tile: B fragments of chunk 0/1 and the output map
     struct Tile {
-      T bv[2][8];
+      T bv[NCH][8];
       const T *xrow;
       int64_t g;
       bool kin;
@@ -783,23 +783,28 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
       const int kk = tl.kin ? kc : K - 1;
       tl.xrow = P.X + (int64_t)cx[kk] * P.ldx;
       tl.g = cg[kk];
-      ldrun(tl.xrow, kq * 8, tl.kin, tl.bv[0]);
-      if (nch > 1) ldrun(tl.xrow, 32 + kq * 8, tl.kin, tl.bv[1]);
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) ldrun(tl.xrow, ch * 32 + kq * 8, tl.kin && ch < nch, tl.bv[ch]);
     };
+    // one tile's products, split over two independent accumulator chains
     auto do_tile = [&](const Tile &tl) {
-      V acc = V{};
+      V acc0 = V{}, acc1 = V{};
 #pragma unroll
-      for (int s = 0; s < 8; ++s) acc = mfma(af[0][s], tl.bv[0][s], acc);
-      if (nch > 1) {
+      for (int ch = 0; ch < NCH; ++ch)
 #pragma unroll
-        for (int s = 0; s < 8; ++s) acc = mfma(af[1][s], tl.bv[1][s], acc);
-      }
-      for (int ch = 2; ch < nch; ++ch) {
+        for (int s = 0; s < 8; s += 2) {
+          acc0 = mfma(af[ch][s], tl.bv[ch][s], acc0);
+          acc1 = mfma(af[ch][s + 1], tl.bv[ch][s + 1], acc1);
+        }
+      for (int ch = NCH; ch < nch; ++ch) {
         T av[8], bv[8];
         ldrun(dyrow, ch * 32 + kq * 8, p < b, av);
         ldrun(tl.xrow, ch * 32 + kq * 8, tl.kin, bv);
 #pragma unroll
-        for (int s = 0; s < 8; ++s) acc = mfma(av[s], bv[s], acc);
+        for (int s = 0; s < 8; s += 2) {
+          acc0 = mfma(av[s], bv[s], acc0);
+          acc1 = mfma(av[s + 1], bv[s + 1], acc1);
+        }
       }
       if (tl.kin) {
         const int64_t base = tl.g >> 7;
@@ -807,20 +812,16 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int pr = mt * 16 + dst_row<T>(kq, i);
-          if (pr < b) P.dA[base + (int64_t)pr * bj] = acc[i];
+          if (pr < b) P.dA[base + (int64_t)pr * bj] = acc0[i] + acc1[i];
         }
       }
     };
-    // ping-pong: the next tile's operands load while the current one multiplies
-    Tile t0, t1;
-    load_tile(0, t0);
-    for (int j = 0; j < ntiles; j += 2) {
-      if (j + 1 < ntiles) load_tile(j + 1, t1);
+    // one tile at a time: other waves hide the load latency (a prefetched
+    // second tile raised register use enough to cost more than it hid)
+    for (int j = 0; j < ntiles; ++j) {
+      Tile t0;
+      load_tile(j, t0);
       do_tile(t0);
-      if (j + 1 < ntiles) {
-        if (j + 2 < ntiles) load_tile(j + 2, t0);
-        do_tile(t1);
-      }
     }
   }
 }
@@ -965,17 +966,22 @@ hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void
   return hipGetLastError();
 }
 
-hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s) {
+template <typename T>
+hipError_t launch_sddmm_t(const SddmmParams<T> &p, hipStream_t s) {
   if (p.nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sddmm_mfma<double>, dim3((unsigned)product_workgroups(p.nrows)),
-                     dim3(kThreads), 0, s, p);
+  const dim3 grid((unsigned)product_workgroups(p.nrows));
+  // right-hand sides beyond the register-resident chunks are loaded per tile
+  if (p.nrhs <= 32)
+    hipLaunchKernelGGL((k_sddmm_mfma<T, 1>), grid, dim3(kThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_sddmm_mfma<T, 2>), grid, dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
+hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s) {
+  return launch_sddmm_t(p, s);
+}
 hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s) {
-  if (p.nrows == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sddmm_mfma<float>, dim3((unsigned)product_workgroups(p.nrows)),
-                     dim3(kThreads), 0, s, p);
-  return hipGetLastError();
+  return launch_sddmm_t(p, s);
 }
 
 int64_t coldot_chunks(int64_t nrows) { return (nrows + kDotRows - 1) / kDotRows; }
