@@ -69,9 +69,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--lattice", type=int, default=32, help="lattice edge (32 = full workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-frac", type=float, default=1.0 / 16,
-                    help="fraction of block rows the CPU oracle processes")
     ap.add_argument("--only", default="", help="comma list of kernels to run (profiling)")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for traffic counters)")
+    ap.add_argument("--sweep", default="",
+                    help="write an nrhs sweep over the workloads (JSON lines) to this file")
     return ap.parse_args()
 
 
@@ -186,7 +188,7 @@ def main():
         roof = {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_TFLOPS[dom_dt],
                 "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_TFLOPS[dom_dt], 4)}
     roof["kernel"] = dom["kernel"]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_record(dom["kernel"])
 
     kernel_ms = sum(r["avg_ms"] for r in rows)
     value = total_bytes / (ms_step * 1e-3) / 1e9
@@ -218,56 +220,200 @@ def main():
         if len(fb) == 3 else None,
         "setup_s": {"generate": round(gen_s, 2), "create_4_handles": round(create_s, 2)},
     }
+    if args.calib:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(5):
+            dst.copy_(src)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out["copy_calib"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                             "gbs": round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+    if args.sweep:
+        run_sweep(args.sweep)
     if not args.no_cpu and len(kernels) == 7:
-        out["cpu_baseline"] = cpu_baseline(op, opc, X1, X32, G32, R64, total_bytes, args.cpu_frac)
+        out["cpu_baseline"] = cpu_baseline(op, opc, X1, X32, G32, R64, total_bytes)
     print(json.dumps(out))
 
 
-def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, frac):
-    """The FP64 oracle on the first ``frac`` of the block rows of every product
-    of the step (its scalar-CSR expansion and transpose are set-up, excluded
-    like the device planner); the step time is extrapolated by 1/frac."""
-    import oracle
-    from workloads.core import Operator
+def _time_call(fn, warm=3, reps=7):
+    """Median of ``reps`` HIP-event timings after ``warm`` untimed calls."""
+    import torch
+    for _ in range(warm):
+        fn()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
 
-    nrow_atoms = max(1, int(op.n * frac))
-    nsr = int(op.off[nrow_atoms])
-    rows = np.arange(nsr, dtype=np.int64)
+
+def run_sweep(path):
+    """nrhs sweep of the forward/adjoint products over the workloads, and the
+    fwd+bwd form of the 100k-atom FP32 operator against plain FP64.  One JSON
+    object per line in ``path``; the paper's timing protocol (median of 7
+    after 3 warm-ups)."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads import make_config
+
+    dev = torch.device("cuda", 0)
+    out = open(path, "w")
+
+    def emit(rec):
+        out.write(json.dumps(rec) + "\n")
+        out.flush()
+        print("sweep", rec["workload"], rec["op"], rec["prec"], rec["nrhs"], rec["ms"],
+              rec.get("hbm_frac"), flush=True)
+
+    def rate(op, prec, nrhs, ms, kind="product"):
+        s_v = {"fp64": 8, "fp32": 4, "bf16x3": 4}[prec]
+        s_x = 8 if prec == "fp64" else 4
+        nbytes = algorithmic_bytes(op, nrhs, s_v, s_x, kind)
+        flops = 2.0 * op.nnz * nrhs
+        peak = PEAK_TFLOPS["fp64" if prec == "fp64" else ("fp32" if prec == "fp32" else "bf16")]
+        roof = max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (peak * 1e12)) * 1e3
+        return {"ms": round(ms, 5), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                "tflops": round(flops / (ms * 1e-3) / 1e12, 3),
+                "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "roofline_frac": round(roof / ms, 4), "alg_bytes": int(nbytes)}
+
+    plan = [("C1", [("fp64", (1, 2, 4, 8, 16), True)]),
+            ("C2", [("fp64", (1, 2, 4, 8, 16, 32, 64), True), ("fp32", (1, 8, 64), False),
+                    ("bf16x3", (64,), False)]),
+            ("C3", [("fp64", (1, 2, 4, 8, 64), True)])]
+    for name, forms in plan:
+        op, _ = make_config(name, nrhs=1)
+        size = {"workload": name, "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz}
+        for prec, nrhss, with_t in forms:
+            A = Matrix.from_operator(op, prec=prec)
+            dt = torch.float64 if prec == "fp64" else torch.float32
+            for nrhs in nrhss:
+                X = torch.randn((op.N, nrhs), dtype=dt, device=dev)
+                Y = torch.empty_like(X)
+                ms = _time_call(lambda: A.spmm(X, Y))
+                emit(dict(size, op="spmm", prec=prec, nrhs=nrhs, **rate(op, prec, nrhs, ms),
+                          cache_resident=bool(op.nnz * (8 if prec == "fp64" else 4) < 256e6)))
+                if with_t and nrhs in (1, 8, 32, 64):
+                    ms = _time_call(lambda: A.spmm_t(X, Y))
+                    emit(dict(size, op="spmm_t", prec=prec, nrhs=nrhs, **rate(op, prec, nrhs, ms),
+                              cache_resident=bool(op.nnz * 8 < 256e6)))
+                del X, Y
+            A.close()
+        del op
+    # differentiation form: forward + adjoint + block-sampled product
+    op, vec = make_config("C5")
+    size = {"workload": "C5", "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz}
+    fb = {}
+    for prec in ("fp32", "fp64"):
+        A = Matrix.from_operator(op, prec=prec)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        X = torch.from_numpy(vec["X"]).to(dev, dt)
+        G = torch.from_numpy(vec["G"]).to(dev, dt)
+        Y, dX = torch.empty_like(X), torch.empty_like(X)
+        dA = torch.empty(op.nnz, dtype=dt, device=dev)
+        t_f = _time_call(lambda: A.spmm(X, Y))
+        t_t = _time_call(lambda: A.spmm_t(G, dX))
+        t_s = _time_call(lambda: A.sddmm(G, X, dA))
+        t_all = _time_call(lambda: (A.spmm(X, Y), A.spmm_t(G, dX), A.sddmm(G, X, dA)))
+        fb[prec] = t_all
+        emit(dict(size, op="spmm", prec=prec, nrhs=32, **rate(op, prec, 32, t_f)))
+        emit(dict(size, op="spmm_t", prec=prec, nrhs=32, **rate(op, prec, 32, t_t)))
+        emit(dict(size, op="sddmm", prec=prec, nrhs=32, **rate(op, prec, 32, t_s, "sddmm")))
+        emit(dict(size, op="fwd+bwd", prec=prec, nrhs=32, ms=round(t_all, 5),
+                  fwd_ms=round(t_f, 5)))
+        A.close()
+    emit(dict(size, op="fwd+bwd ratio fp32/fp64", prec="fp32", nrhs=32,
+              ms=round(fb["fp32"], 5), ratio=round(fb["fp32"] / fb["fp64"], 4)))
+    out.close()
+
+
+def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, budget_s=12.0):
+    """The FP64 oracle (all host cores) on every product of the step, full
+    size, repeated until about ``budget_s`` seconds of CPU work are timed;
+    the oracle's scalar-CSR expansion and transpose are set-up, excluded like
+    the device planner.  Every precision form runs as the FP64 oracle."""
+    import oracle
+
     A = oracle.expand_op(op)
     At = oracle.transpose(A)
     Ac = oracle.expand_op(opc)
-    # sub-operator of the first block rows for the block-sampled product
-    nb = int(op.row_ptr[nrow_atoms])
-    sub = Operator("sub", op.b, np.concatenate([op.row_ptr[:nrow_atoms + 1],
-                                                np.full(op.n - nrow_atoms, nb)]),
-                   op.col_idx[:nb], op.values[:int(op.block_base[nb])], op.dist[:nb])
     T = np.random.default_rng(5).uniform(-1, 1, (op.N, 64))
-    t = {}
-    t0 = time.perf_counter()
-    oracle.csr_spmm_rows(A, X1, rows)
-    t["spmv_fp64"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.csr_spmm_rows(A, X32, rows)
-    t["spmm_fp64"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.csr_spmm_rows(At, G32, rows)
-    t["spmm_t_fp64"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.sddmm(sub, G32, X32)
-    t["sddmm_fp64"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.csr_spmm_rows(Ac, T, rows)
-    tc = time.perf_counter() - t0
-    for k in ("cheb_fp64", "cheb_fp32", "cheb_bf16x3"):
-        t[k] = tc      # the oracle computes every precision form in FP64
-    f = nsr / op.N
-    est = sum(t.values()) / f
-    return {"value": round(step_bytes / est / 1e9, 3), "unit": "GB/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": "first %d of %d block rows (%d scalar rows) of each of the 7 products; "
-                      "FP64 scalar-CSR oracle, measured %.2f s, extrapolated step %.2f s"
-                      % (nrow_atoms, op.n, nsr, sum(t.values()), est),
-            "per_kernel_s": {k: round(v / f, 3) for k, v in t.items()}}
+    Tp = np.random.default_rng(6).uniform(-1, 1, (op.N, 64))
+    names = ["spmv_fp64", "spmm_fp64", "spmm_t_fp64", "sddmm_fp64", "cheb_fp64", "cheb_fp32",
+             "cheb_bf16x3"]
+    per = {k: [] for k in names}
+    reps = 0
+    t_all = time.perf_counter()
+    while True:
+        t = {}
+        t0 = time.perf_counter()
+        oracle.csr_spmm(A, X1)
+        t["spmv_fp64"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.csr_spmm(A, X32)
+        t["spmm_fp64"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.csr_spmm(At, G32)
+        t["spmm_t_fp64"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.sddmm(op, G32, X32)
+        t["sddmm_fp64"] = time.perf_counter() - t0
+        for k in ("cheb_fp64", "cheb_fp32", "cheb_bf16x3"):
+            t0 = time.perf_counter()
+            Y = oracle.csr_spmm(Ac, T, alpha=2.0, beta=-1.0, Y=Tp)
+            (R64 * Y).sum(axis=0)
+            t[k] = time.perf_counter() - t0
+        reps += 1
+        for k in names:
+            per[k].append(t[k])
+        if time.perf_counter() - t_all >= budget_s or reps >= 7:
+            break
+    med = {k: float(np.median(v)) for k, v in per.items()}
+    step_s = sum(med.values())
+    return {"value": round(step_bytes / step_s / 1e9, 3), "unit": "GB/s",
+            "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": "the whole step (7 products, full size) on the FP64 scalar-CSR oracle, "
+                      "median of %d repetitions (%.1f s of CPU work); expansion/transpose "
+                      "excluded; FP32/BF16x3 forms run as FP64" % (reps, time.perf_counter() - t_all),
+            "step_s": round(step_s, 4),
+            "per_kernel_s": {k: round(v, 4) for k, v in med.items()}}
+
+
+def traffic_record(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"<!-- traffic: (\{.*\}) -->", open(path).read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("sha") != kernel_source_sha():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return int(k["fetch_bytes"] + k["write_bytes"])
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "abi.cpp", "planner.cpp", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2609_04397_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 if __name__ == "__main__":
