@@ -91,8 +91,9 @@ typedef struct {
  *   stream       stream used for the initial upload (synchronised before return)
  *
  * The caller keeps ownership of every input array; the library deep-copies.
- * Errors: EINVAL, ESHAPE, EDUP, EUNSUPPORTED (b_i > VBCSR_MAX_BLOCK or
- * N > 2^31-1), ENOMEM, EHIP.
+ * Errors: EINVAL, ESHAPE, EDUP, EUNSUPPORTED (b_i > VBCSR_MAX_BLOCK,
+ * N > 2^31-1, or one block row or block column with 2^28 or more values),
+ * ENOMEM, EHIP.
  */
 int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
                  const int64_t *row_ptr, const int32_t *col_idx, const double *values,

@@ -210,6 +210,7 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
     p.vals = static_cast<const double *>(D.vals);
     p.X = static_cast<const double *>(X);
     p.ldx = ldx;
+    p.xrows = A->N;
     p.Yin = static_cast<const double *>(Yin);
     p.ldyin = ldyin;
     p.Yout = static_cast<double *>(Yout);
@@ -232,6 +233,7 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
     p.vbase16 = D.vbase16;
     p.X = static_cast<const float *>(X);
     p.ldx = ldx;
+    p.xrows = A->N;
     p.Yin = static_cast<const float *>(Yin);
     p.ldyin = ldyin;
     p.Yout = static_cast<float *>(Yout);

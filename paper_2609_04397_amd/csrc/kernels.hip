@@ -34,6 +34,14 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u __attribute__((ext_vector_type(8)));
 
+// Index of the calling wave in its workgroup.  The shift is the same for all
+// lanes of a wave, but the compiler cannot see that; reading it from the
+// first lane puts it (and every row descriptor, address and buffer resource
+// derived from it) in scalar registers.
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Give every XCD one contiguous range of logical workgroups so that
 // panels that share input rows (spatial neighbours) share an L2.
@@ -119,39 +127,6 @@ __device__ __forceinline__ T stream_load(const T *p) {
   return __builtin_nontemporal_load(p);
 }
 
-// Gather the X rows of panel columns [kc, kc + kn) into a wave-private LDS
-// tile xs[col * NRP + c] (NRP >= nc values per row, zero-padded).  Each lane
-// owns whole columns: the column indices of up to CPL columns per lane are
-// loaded first, then every X load, then the LDS writes, so a chunk costs two
-// memory round trips however many columns it holds.
-template <typename T, int NRP, int CPL>
-__device__ __forceinline__ void stage_x(T *xs, const int32_t *__restrict__ cx, const T *__restrict__ X,
-                                        int64_t ldx, int c0, int nc, int kc, int kn, int lane) {
-  for (int k0 = 0; k0 < kn; k0 += 64 * CPL) {
-    int32_t xr[CPL];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const int k = k0 + j * 64 + lane;
-      xr[j] = k < kn ? cx[kc + k] : -1;
-    }
-    T v[CPL][NRP];
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const T *xp = X + (int64_t)(xr[j] >= 0 ? xr[j] : 0) * ldx + c0;
-#pragma unroll
-      for (int c = 0; c < NRP; ++c) v[j][c] = (xr[j] >= 0 && c < nc) ? xp[c] : T(0);
-    }
-#pragma unroll
-    for (int j = 0; j < CPL; ++j) {
-      const int k = k0 + j * 64 + lane;
-      if (k < kn) {
-#pragma unroll
-        for (int c = 0; c < NRP; ++c) xs[k * NRP + c] = v[j][c];
-      }
-    }
-  }
-}
-
 // Raw buffer access to one panel: the descriptor (base, size in bytes) is
 // wave-uniform and lives in scalar registers, each lane supplies a 32-bit
 // byte offset, and offsets at or beyond the size read as zero.  Panel value
@@ -167,6 +142,55 @@ template <> __device__ __forceinline__ double buf_load_nt<double>(__amdgpu_buffe
 }
 template <> __device__ __forceinline__ float buf_load_nt<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+template <typename T> __device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <> __device__ __forceinline__ double buf_load<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// 64 zeros, read in place of an X row where a lane has none (padding slices,
+// columns past a staged chunk, right-hand sides past nrhs); any T of <= 8 bytes
+__device__ double kZeroRow[64] = {};  // never written
+template <typename T> __device__ __forceinline__ const T *zero_row() {
+  return reinterpret_cast<const T *>(kZeroRow);
+}
+
+// Gather the X rows of panel columns [kc, kc + kn) into a wave-private LDS
+// tile xs[col * NRP + c] (NRP >= nc values per row, zero-padded).  Each lane
+// owns whole columns: the column indices of up to CPL columns per lane are
+// loaded first, then every X load, then the LDS writes, so a chunk costs two
+// memory round trips however many columns it holds.  The loads carry no
+// branches: indices past the chunk read zero from the buffer and columns
+// past the chunk (or right-hand sides past nc) read the row of zeros.
+template <typename T, int NRP, int CPL>
+__device__ __forceinline__ void stage_x(T *xs, const int32_t *__restrict__ cx, const T *__restrict__ X,
+                                        int64_t ldx, int c0, int nc, int kc, int kn, int lane) {
+  const __amdgpu_buffer_rsrc_t rc = panel_rsrc(cx + kc, (uint32_t)kn * 4);
+  for (int k0 = 0; k0 < kn; k0 += 64 * CPL) {
+    int32_t xr[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+      xr[j] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)(k0 + j * 64 + lane) * 4, 0, 0);
+    T v[CPL][NRP];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int k = k0 + j * 64 + lane;
+      const T *xp = k < kn ? X + (int64_t)xr[j] * ldx + c0 : zero_row<T>();
+#pragma unroll
+      for (int c = 0; c < NRP; ++c) v[j][c] = (c < nc ? xp : zero_row<T>())[c];
+    }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int k = k0 + j * 64 + lane;
+      if (k < kn) {
+#pragma unroll
+        for (int c = 0; c < NRP; ++c) xs[k * NRP + c] = v[j][c];
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -185,7 +209,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
   constexpr int U = NR <= 2 ? 4 : 2;
   __shared__ T xs_all[kWaves * XCAP];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
   T *xs = xs_all + w * XCAP;
@@ -285,8 +309,14 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
 // ---------------------------------------------------------------------------
 // A operand: the panel's 4-column slice (contiguous, 4*b values, panel row m
 // in lane m, slice column kq in lane group kq); B operand: the X rows of
-// those 4 columns.  The values and column indices of the next U slices are
-// in flight while the current U slices multiply.
+// those 4 columns.  Slices are taken in groups of U.  Two register sets
+// alternate: while one group multiplies, the values and X rows of the next
+// group and the column indices of the one after are in flight.  The loop
+// has no data-dependent branch (a branch around a load makes the compiler
+// wait for every load in flight): values and indices are buffer loads that
+// read zero past the panel, and padding slices point at a row of zeros
+// instead of a row of X.  Scheduling barriers keep each group's loads ahead
+// of the previous group's matrix instructions.
 //
 // Fast path (VX = true): the N index of the 16x16 tiles is permuted so that
 // lane m of tile t holds right-hand side c0 + l*16*VEC + VEC*m + e, with
@@ -299,17 +329,17 @@ template <typename T> struct Vec16;
 template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
 template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
 
-template <typename T, int NT, bool MOM, bool VX>
+template <typename T, int NT, bool MOM, bool VX, bool XB>
 __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
   extern __shared__ double s_mom[];
   using V = typename Frag<T>::type;
   using L16 = typename Vec16<T>::type;
   constexpr int VEC = Vec16<T>::n;
   constexpr int NL = VX ? NT / VEC : 0;  // 16-byte loads per lane and X row
-  constexpr int U = 4;
+  constexpr int U = NT * sizeof(T) >= 32 ? 2 : 4;  // slices per group
   static_assert(!VX || NT % VEC == 0, "tile count must fill whole 16-byte loads");
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
   const int m = lane & 15;   // A: panel row in the tile; B and D: column in the tile
@@ -332,53 +362,99 @@ __global__ void __launch_bounds__(kThreads) k_spmm_mfma(FwdParams<T> P) {
         V acc[NT];
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = V{};
-        T a[U];
-        int32_t xr[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int k = u * 4 + kq;
-          const bool kin = k < K;
-          a[u] = (kin && prow) ? stream_load(vals + (int64_t)k * b + p) : T(0);
-          xr[u] = kin ? cx[k] : -1;
-        }
-        for (int s = 0; s < nsteps; s += U) {
-          T xv[U][NT];
+        // panel sizes are below 2^31 bytes (checked at creation), so kOut is
+        // past the end of every panel and reads zero
+        constexpr uint32_t kOut = 0x80000000u;
+        const __amdgpu_buffer_rsrc_t rv = panel_rsrc(vals, (uint32_t)((int64_t)K * b * sizeof(T)));
+        const __amdgpu_buffer_rsrc_t rc = panel_rsrc(cx, (uint32_t)(K * 4));
+        const uint32_t vlane = prow ? (uint32_t)(kq * b + p) * sizeof(T) : kOut;
+        // XB: all of X lies within 2^31 bytes and is read through one buffer
+        // descriptor (cheaper addressing); otherwise through 64-bit pointers
+        const __amdgpu_buffer_rsrc_t rx =
+            panel_rsrc(P.X, XB ? (uint32_t)(P.xrows * P.ldx * (int64_t)sizeof(T)) : 0u);
+        const uint32_t xcol = (uint32_t)(c0 + (VX ? VEC * m : m)) * sizeof(T);
+        auto ld_idx = [&](int g, int32_t(&xi)[U]) {
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            const T *xp = P.X + (int64_t)xr[u] * P.ldx + c0;
-            if constexpr (VX) {
+            const int k = (g * U + u) * 4 + kq;
+            const int32_t v = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)k * 4, 0, 0);
+            xi[u] = k < K ? v : -1;
+          }
+        };
+        auto ld_val = [&](int g, T(&av)[U]) {
 #pragma unroll
-              for (int l = 0; l < (VX ? NL : 1); ++l) {
-                L16 q = xr[u] >= 0 ? *reinterpret_cast<const L16 *>(xp + l * 16 * VEC + VEC * m)
-                                   : L16{};
-                const T *qe = reinterpret_cast<const T *>(&q);
+          for (int u = 0; u < U; ++u)
+            av[u] = buf_load_nt<T>(rv, vlane + (uint32_t)((g * U + u) * 4 * b) * sizeof(T));
+        };
+        auto ld_x = [&](const int32_t(&xi)[U], T(&xv)[U][NT]) {
 #pragma unroll
-                for (int e = 0; e < VEC; ++e) xv[u][l * VEC + e] = qe[e];
+          for (int u = 0; u < U; ++u) {
+            if constexpr (XB) {
+              // padding slices read past the descriptor: zeros
+              const uint32_t ro =
+                  xi[u] >= 0 ? (uint32_t)((int64_t)xi[u] * P.ldx * (int64_t)sizeof(T)) + xcol : kOut;
+              if constexpr (VX) {
+#pragma unroll
+                for (int l = 0; l < (VX ? NL : 1); ++l) {
+                  const L16 q = __builtin_bit_cast(
+                      L16, __builtin_amdgcn_raw_buffer_load_b128(rx, ro + l * 16 * VEC * sizeof(T), 0, 0));
+                  const T *qe = reinterpret_cast<const T *>(&q);
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) xv[u][l * VEC + e] = qe[e];
+                }
+              } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                  xv[u][t] = buf_load<T>(rx, c0 + t * 16 + m < P.nrhs ? ro + t * 16 * sizeof(T) : kOut);
               }
             } else {
+              // padding slices read a row of zeros instead of a row of X
+              const T *xp = xi[u] >= 0 ? P.X + (int64_t)xi[u] * P.ldx + c0 : zero_row<T>();
+              if constexpr (VX) {
 #pragma unroll
-              for (int t = 0; t < NT; ++t)
-                xv[u][t] = (xr[u] >= 0 && c0 + t * 16 + m < P.nrhs) ? xp[t * 16 + m] : T(0);
+                for (int l = 0; l < (VX ? NL : 1); ++l) {
+                  const L16 q = *reinterpret_cast<const L16 *>(xp + l * 16 * VEC + VEC * m);
+                  const T *qe = reinterpret_cast<const T *>(&q);
+#pragma unroll
+                  for (int e = 0; e < VEC; ++e) xv[u][l * VEC + e] = qe[e];
+                }
+              } else {
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                  const int n = t * 16 + m;
+                  xv[u][t] = (c0 + n < P.nrhs ? xp : zero_row<T>())[n];
+                }
+              }
             }
           }
-          T an[U];
-          int32_t xn[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const int k = (s + U + u) * 4 + kq;
-            const bool kin = k < K;
-            an[u] = (kin && prow) ? stream_load(vals + (int64_t)k * b + p) : T(0);
-            xn[u] = kin ? cx[k] : -1;
-          }
+        };
+        auto mma = [&](const T(&av)[U], const T(&xv)[U][NT]) {
 #pragma unroll
           for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = mfma(a[u], xv[u][t], acc[t]);
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            a[u] = an[u];
-            xr[u] = xn[u];
-          }
+            for (int t = 0; t < NT; ++t) acc[t] = mfma(av[u], xv[u][t], acc[t]);
+        };
+        const int ngroups = (nsteps + U - 1) / U;
+        T aA[U], aB[U], vA[U][NT], vB[U][NT];
+        int32_t iA[U], iB[U];
+        ld_idx(0, iA);
+        ld_idx(1, iB);
+        ld_x(iA, vA);
+        ld_val(0, aA);
+        for (int g = 0; g < ngroups; g += 2) {
+          ld_idx(g + 2, iA);
+          ld_x(iB, vB);
+          ld_val(g + 1, aB);
+          __builtin_amdgcn_sched_barrier(0);
+          mma(aA, vA);
+          __builtin_amdgcn_sched_barrier(0);
+          if (g + 1 >= ngroups) break;
+          ld_idx(g + 3, iB);
+          ld_x(iA, vA);
+          ld_val(g + 2, aA);
+          __builtin_amdgcn_sched_barrier(0);
+          mma(aB, vB);
+          __builtin_amdgcn_sched_barrier(0);
         }
         // epilogue: row pr of the tile, columns col(t)
         double mmv[NT];
@@ -455,7 +531,7 @@ template <int NT, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
   extern __shared__ double s_mom[];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
   const int m = lane & 15;
@@ -572,7 +648,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
   extern __shared__ double s_mom[];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
-  const int w = threadIdx.x >> 6;
+  const int w = wave_id();
   const int lane = threadIdx.x & 63;
   const int row = wg * kWaves + w;
   const int m = lane & 15;
@@ -689,7 +765,7 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src, int src_dtype,
                                                    void *dst, int dst_kind, uint16_t *dst_lo) {
-  const int64_t k = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  const int64_t k = (int64_t)blockIdx.x * kWaves + wave_id();
   if (k >= P.nnzb) return;
   const int lane = threadIdx.x & 63;
   const int i = P.blk_row[k], j = P.col_idx[k];
@@ -735,7 +811,7 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
 template <typename T, int NCH>
 __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   using V = typename Frag<T>::type;
-  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
   if (row >= P.nrows) return;
   const int lane = threadIdx.x & 63;
   const int m = lane & 15;
@@ -870,13 +946,21 @@ hipError_t launch_vec_nr(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t
   return hipGetLastError();
 }
 
+template <typename T, int NT, bool VX, bool XB>
+hipError_t launch_mfma_xb(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
+  if (p.mom)
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, true, VX, XB>), grid, dim3(kThreads), shm, s, p);
+  else
+    hipLaunchKernelGGL((k_spmm_mfma<T, NT, false, VX, XB>), grid, dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
 template <typename T, int NT, bool VX>
 hipError_t launch_mfma_nt(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
-  if (p.mom)
-    hipLaunchKernelGGL((k_spmm_mfma<T, NT, true, VX>), grid, dim3(kThreads), shm, s, p);
-  else
-    hipLaunchKernelGGL((k_spmm_mfma<T, NT, false, VX>), grid, dim3(kThreads), 0, s, p);
-  return hipGetLastError();
+  // one buffer descriptor covers X when its rows span less than 2^31 bytes
+  if (p.xrows * p.ldx * (int64_t)sizeof(T) < (int64_t(1) << 31))
+    return launch_mfma_xb<T, NT, VX, true>(p, s, grid, shm);
+  return launch_mfma_xb<T, NT, VX, false>(p, s, grid, shm);
 }
 
 // The vectorised fast path applies when every vector is 16-byte aligned,

@@ -24,6 +24,7 @@ struct FwdParams {
   const int64_t *vbase16;
   const T *X;
   int64_t ldx;
+  int64_t xrows;        // rows of X (columns of the operator)
   const T *Yin;
   int64_t ldyin;
   T *Yout;

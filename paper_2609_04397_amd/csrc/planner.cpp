@@ -54,6 +54,26 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
     err = "n_values " + std::to_string(n_values) + " != sum of block sizes " + std::to_string(nnz);
     return VBCSR_ESHAPE;
   }
+  // The kernels address one block row (forward) or block column (adjoint)
+  // with 32-bit byte offsets: its values must stay below 2^31 bytes in FP64.
+  constexpr int64_t kPanelMax = (int64_t(1) << 31) / 8;
+  std::vector<int64_t> colk(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    int64_t k = 0;
+    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+      k += b[col_idx[e]];
+      colk[col_idx[e]] += b[i];
+    }
+    if (k * b[i] >= kPanelMax) {
+      err = "block row " + std::to_string(i) + " holds 2^28 or more values";
+      return VBCSR_EUNSUPPORTED;
+    }
+  }
+  for (int32_t j = 0; j < n; ++j)
+    if (colk[j] * b[j] >= kPanelMax) {
+      err = "block column " + std::to_string(j) + " holds 2^28 or more values";
+      return VBCSR_EUNSUPPORTED;
+    }
   return VBCSR_OK;
 }
 

@@ -132,6 +132,33 @@ def test_validation_errors(lib):
     assert "exceeds" in msg
 
 
+def test_panel_size_limit(lib):
+    """One block row (or block column) holding 2^28 values is refused: the
+    kernels address a panel with 32-bit byte offsets."""
+    n = 1 << 16
+    b = np.full(n, 64, np.int32)
+    nval = 64 * 64 * n
+    # every block in row 0
+    rp = np.full(n + 1, n, np.int64)
+    rp[0] = 0
+    ci = np.arange(n, dtype=np.int32)
+    assert _case(lib, b, rp, ci, nval) == _lib.VBCSR_EUNSUPPORTED
+    assert "block row 0" in lib.vbcsr_last_error().decode()
+    # every block in column 0
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.zeros(n, np.int32)
+    assert _case(lib, b, rp, ci, nval) == _lib.VBCSR_EUNSUPPORTED
+    assert "block column 0" in lib.vbcsr_last_error().decode()
+    # one block fewer in the row is accepted by the validation
+    b2 = b.copy()
+    b2[-1] = 63
+    rp = np.full(n + 1, n, np.int64)
+    rp[0] = 0
+    ci = np.arange(n, dtype=np.int32)
+    rc = _case(lib, b2, rp, ci, 64 * 64 * (n - 1) + 64 * 63)
+    assert rc == _lib.VBCSR_OK
+
+
 def test_empty_graph_is_valid(lib):
     rc, ns, _, pv = _plan(lib, np.zeros(0, np.int32), np.zeros(1, np.int64), np.zeros(0, np.int32), 0)
     assert rc == 0 and ns == 0 and pv == 0

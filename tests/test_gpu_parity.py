@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_util import dev, host, check, rounded, TOL
+from gpu_util import dev, host, check, rounded, TOL, DT
 from metrics import rel_f, comp
 from workloads import random_pattern, make_config, sc_lattice
 
@@ -112,6 +112,32 @@ def test_strided_vectors():
     y = host(Yd)
     check(y[:, 1:6], oracle.spmm(op, Xbig[:, 2:7]), "fp64", oracle.abs_product(op, Xbig[:, 2:7]))
     assert np.all(y[:, :1] == 0) and np.all(y[:, 6:] == 0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_x_rows_beyond_2gib(prec):
+    """X whose rows span more than 2^31 bytes (large leading dimension): the
+    matrix-core kernels then read it through 64-bit pointers instead of one
+    buffer descriptor; the vector kernel always does."""
+    op = random_pattern(15, 60, bset=(4, 9, 13), density=0.2, empty_rows=1)
+    s = 8 if prec == "fp64" else 4
+    ld = ((1 << 31) // (s * op.N) + 64) // 4 * 4
+    assert op.N * ld * s > (1 << 31)
+    print("case big-ld", prec, op.N, ld, flush=True)
+    X = np.random.default_rng(5).standard_normal((op.N, 40))
+    big = torch.zeros((op.N, ld), dtype=DT[prec], device="cuda")
+    big[:, :40] = dev(X, prec)
+    for path, nrhs in (("mfma", 32), ("mfma", 40), ("vec", 3)):
+        A = Matrix.from_operator(op, prec=prec, path=path)
+        Xr = rounded(X[:, :nrhs], prec)
+        for transpose in (False, True):
+            ref = (oracle.spmm_t if transpose else oracle.spmm)(op, Xr)
+            got = host(A.spmm(big[:, :nrhs], transpose=transpose))
+            scale = oracle.abs_product(op, Xr, transpose_op=transpose) if prec == "fp64" else None
+            check(got, ref, prec, scale, "big ld %s %s nrhs=%d T=%s" % (prec, path, nrhs, transpose))
+        A.close()
+    del big
+    torch.cuda.empty_cache()
 
 
 def test_argument_errors_on_device():
