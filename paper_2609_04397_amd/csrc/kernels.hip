@@ -637,13 +637,14 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3(FwdParams<float> P) {
 // BF16x3 fast path: 64 right-hand sides per pass, tile t of lane m holds
 // column c0 + 4m + t, so the 8 X rows of a lane's 8-column group arrive as
 // eight 16-byte loads; each row splits into hi/lo with the hardware
-// round-to-nearest-even conversion (two values per instruction).
+// round-to-nearest-even conversion (two values per instruction).  The loop
+// is branch-free and double-buffered like the FP64/FP32 matrix-core kernel.
 typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ unsigned int pack_bf16(float a, float b) {
   return __builtin_bit_cast(unsigned int, v2bf{(__bf16)a, (__bf16)b});
 }
 
-template <bool MOM>
+template <bool MOM, bool XB>
 __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P) {
   extern __shared__ double s_mom[];
   typedef unsigned int v4u __attribute__((ext_vector_type(4)));
@@ -660,43 +661,55 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
     const int ngroups = (K + 7) >> 3;
     const int nsteps = (K + 31) >> 5;
     const int64_t vb16 = P.vbase16[row];
-    const int32_t *__restrict__ cx = P.colx + rd.cbase;
+    constexpr uint32_t kOut = 0x80000000u;
+    // the row's BF16 pages, its column table and (XB) all of X, each read
+    // through one buffer descriptor; offsets past the end read zero
+    const uint32_t pbytes = (uint32_t)((int64_t)ngroups * 8 * b * sizeof(uint16_t));
+    const __amdgpu_buffer_rsrc_t rh = panel_rsrc(P.hi + vb16, pbytes);
+    const __amdgpu_buffer_rsrc_t rl = panel_rsrc(P.lo + vb16, pbytes);
+    const __amdgpu_buffer_rsrc_t rc = panel_rsrc(P.colx + rd.cbase, (uint32_t)(K * 4));
+    const __amdgpu_buffer_rsrc_t rx =
+        panel_rsrc(P.X, XB ? (uint32_t)(P.xrows * P.ldx * (int64_t)sizeof(float)) : 0u);
     for (int mt = 0; mt * 16 < b; ++mt) {
       const int p = mt * 16 + m;
       const bool prow = p < b;
+      const uint32_t vlane = prow ? (uint32_t)(kg * 8 * b + p * 8) * sizeof(uint16_t) : kOut;
       for (int c0 = 0; c0 < P.nrhs; c0 += 64) {
         v4f acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = v4f{};
-        auto fetch = [&](int s, v8u &h, v8u &l, int32_t *x) {
-          const int grp = s * 4 + kg;
-          const bool ok = prow && grp < ngroups;
-          h = v8u{};
-          l = v8u{};
-          if (ok) {
-            const int64_t a = vb16 + (int64_t)grp * 8 * b + p * 8;
-            h = stream_load(reinterpret_cast<const v8u *>(P.hi + a));
-            l = stream_load(reinterpret_cast<const v8u *>(P.lo + a));
-          }
+        const uint32_t xcol = (uint32_t)(c0 + 4 * m) * sizeof(float);
+        // step s covers panel columns [32 s, 32 s + 32); lane group kg holds
+        // the 8 columns 32 s + 8 kg + u.  Two register sets alternate as in
+        // the FP64/FP32 kernel: indices run two steps ahead, values and X
+        // rows one step ahead.
+        auto ld_idx = [&](int s, int32_t(&xi)[8]) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            const int k = grp * 8 + u;
-            x[u] = k < K ? cx[k] : -1;
+            const int k = (s * 4 + kg) * 8 + u;
+            const int32_t v = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)k * 4, 0, 0);
+            xi[u] = k < K ? v : -1;
           }
         };
-        v8u ah, al;
-        int32_t xr[8];
-        fetch(0, ah, al, xr);
-        for (int s = 0; s < nsteps; ++s) {
-          float4 xv[8];
+        auto ld_val = [&](int s, v8u &h, v8u &l) {
+          const uint32_t off = vlane + (uint32_t)(s * 32 * b) * sizeof(uint16_t);
+          h = __builtin_bit_cast(v8u, __builtin_amdgcn_raw_buffer_load_b128(rh, off, 0, 2));
+          l = __builtin_bit_cast(v8u, __builtin_amdgcn_raw_buffer_load_b128(rl, off, 0, 2));
+        };
+        auto ld_x = [&](const int32_t(&xi)[8], float4(&xv)[8]) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            xv[u] = xr[u] >= 0
-                        ? *reinterpret_cast<const float4 *>(P.X + (int64_t)xr[u] * P.ldx + c0 + 4 * m)
-                        : float4{0.f, 0.f, 0.f, 0.f};
-          v8u nh, nl;
-          int32_t xn[8];
-          fetch(s + 1, nh, nl, xn);
+          for (int u = 0; u < 8; ++u) {
+            if constexpr (XB) {
+              const uint32_t ro =
+                  xi[u] >= 0 ? (uint32_t)((int64_t)xi[u] * P.ldx * (int64_t)sizeof(float)) + xcol : kOut;
+              xv[u] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rx, ro, 0, 0));
+            } else {
+              const float *xp = xi[u] >= 0 ? P.X + (int64_t)xi[u] * P.ldx + c0 : zero_row<float>();
+              xv[u] = *reinterpret_cast<const float4 *>(xp + 4 * m);
+            }
+          }
+        };
+        auto mma = [&](const v8u &ah, const v8u &al, const float4(&xv)[8]) {
 #pragma unroll
           for (int t = 0; t < 4; ++t) {
             v4u hi, lo;
@@ -713,10 +726,28 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
             acc[t] = mfma_bf16(ah, xl, acc[t]);
             acc[t] = mfma_bf16(al, xh, acc[t]);
           }
-          ah = nh;
-          al = nl;
-#pragma unroll
-          for (int u = 0; u < 8; ++u) xr[u] = xn[u];
+        };
+        v8u hA, lA, hB, lB;
+        float4 xA[8], xB[8];
+        int32_t iA[8], iB[8];
+        ld_idx(0, iA);
+        ld_idx(1, iB);
+        ld_x(iA, xA);
+        ld_val(0, hA, lA);
+        for (int s = 0; s < nsteps; s += 2) {
+          ld_idx(s + 2, iA);
+          ld_x(iB, xB);
+          ld_val(s + 1, hB, lB);
+          __builtin_amdgcn_sched_barrier(0);
+          mma(hA, lA, xA);
+          __builtin_amdgcn_sched_barrier(0);
+          if (s + 1 >= nsteps) break;
+          ld_idx(s + 3, iB);
+          ld_x(iA, xA);
+          ld_val(s + 2, hA, lA);
+          __builtin_amdgcn_sched_barrier(0);
+          mma(hB, lB, xB);
+          __builtin_amdgcn_sched_barrier(0);
         }
         double mmv[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1003,10 +1034,18 @@ hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t
   if constexpr (std::is_same<T, float>::value) {
     if (kind == Kind::Bf16x3) {
       if (vectorizable(p, 4)) {
-        if (p.mom)
-          hipLaunchKernelGGL((k_spmm_bf16x3_vx<true>), grid, dim3(kThreads), shm, s, p);
-        else
-          hipLaunchKernelGGL((k_spmm_bf16x3_vx<false>), grid, dim3(kThreads), 0, s, p);
+        const bool xb = p.xrows * p.ldx * (int64_t)sizeof(float) < (int64_t(1) << 31);
+        if (p.mom) {
+          if (xb)
+            hipLaunchKernelGGL((k_spmm_bf16x3_vx<true, true>), grid, dim3(kThreads), shm, s, p);
+          else
+            hipLaunchKernelGGL((k_spmm_bf16x3_vx<true, false>), grid, dim3(kThreads), shm, s, p);
+        } else {
+          if (xb)
+            hipLaunchKernelGGL((k_spmm_bf16x3_vx<false, true>), grid, dim3(kThreads), 0, s, p);
+          else
+            hipLaunchKernelGGL((k_spmm_bf16x3_vx<false, false>), grid, dim3(kThreads), 0, s, p);
+        }
         return hipGetLastError();
       }
       switch (tile) {
