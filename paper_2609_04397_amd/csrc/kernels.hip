@@ -33,6 +33,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u __attribute__((ext_vector_type(8)));
+typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
 
 // Index of the calling wave in its workgroup.  The shift is the same for all
 // lanes of a wave, but the compiler cannot see that; reading it from the
@@ -153,7 +154,7 @@ template <> __device__ __forceinline__ float buf_load<float>(__amdgpu_buffer_rsr
 
 // 64 zeros, read in place of an X row where a lane has none (padding slices,
 // columns past a staged chunk, right-hand sides past nrhs); any T of <= 8 bytes
-__device__ double kZeroRow[64] = {};  // never written
+__device__ __align__(16) double kZeroRow[64] = {};  // never written
 template <typename T> __device__ __forceinline__ const T *zero_row() {
   return reinterpret_cast<const T *>(kZeroRow);
 }
@@ -193,6 +194,56 @@ __device__ __forceinline__ void stage_x(T *xs, const int32_t *__restrict__ cx, c
   }
 }
 
+// Same tile from whole pieces of X rows, for full passes (nc = NRP) whose
+// rows start on 16-byte boundaries: LPR lanes share a row and each loads up
+// to 16 bytes of it, so one load instruction brings 64/LPR rows instead of
+// one element of 64 rows.  A lane loads the indices of 64 columns, the
+// others receive theirs through a lane permute, and CB blocks of 64 columns
+// are in flight at a time.
+template <int B> struct Bytes;
+template <> struct Bytes<4> { using type = unsigned int; };
+template <> struct Bytes<8> { using type = unsigned long long; };
+template <> struct Bytes<16> { using type = v4u32; };
+
+template <typename T, int NRP>
+__device__ __forceinline__ void stage_x_rows(T *xs, const int32_t *__restrict__ cx,
+                                             const T *__restrict__ X, int64_t ldx, int c0, int kc,
+                                             int kn, int lane) {
+  constexpr int RB = NRP * (int)sizeof(T);  // bytes of a staged row
+  constexpr int LB = RB >= 16 ? 16 : RB;    // bytes per lane
+  constexpr int LPR = RB / LB;              // lanes per row
+  constexpr int RPI = 64 / LPR;             // rows per load instruction
+  constexpr int EPL = LB / (int)sizeof(T);  // elements per lane
+  constexpr int CB = LPR >= 4 ? 1 : 4 / LPR;
+  using L = typename Bytes<LB>::type;
+  const __amdgpu_buffer_rsrc_t rc = panel_rsrc(cx + kc, (uint32_t)kn * 4);
+  const int sub = (lane % LPR) * EPL;
+  for (int k0 = 0; k0 < kn; k0 += 64 * CB) {
+    int32_t idx[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+      idx[cb] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)(k0 + cb * 64 + lane) * 4, 0, 0);
+    L v[CB][LPR];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const int rl = q * RPI + lane / LPR;
+        const int32_t r = __shfl(idx[cb], rl, 64);
+        const int k = k0 + cb * 64 + rl;
+        const T *xp = (k < kn ? X + (int64_t)r * ldx + c0 : zero_row<T>()) + sub;
+        v[cb][q] = *reinterpret_cast<const L *>(xp);
+      }
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const int k = k0 + cb * 64 + q * RPI + lane / LPR;
+        if (k < kn) *reinterpret_cast<L *>(xs + k * NRP + sub) = v[cb][q];
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // vector-FMA product, NR right-hand sides per pass
 // ---------------------------------------------------------------------------
@@ -200,14 +251,23 @@ __device__ __forceinline__ void stage_x(T *xs, const int32_t *__restrict__ cx, c
 // wave-private LDS buffer, so the value stream never waits on a dependent
 // index -> X load chain.  The values of the next U steps are in flight while
 // the current U steps are multiplied.
-constexpr int kXsBytes = 4096;  // LDS staging per wave
+// Tuning of the two vector kernels, measured on the 32^3 lattice (b = 13),
+// the zincblende particle and the three-species random operator: which pass
+// widths use 16-byte value loads (the kernel after this one), the value
+// loads in flight per lane (steps of look-ahead) and the LDS staging per
+// wave in bytes.
+template <typename T, int NR> constexpr bool use_vp() { return sizeof(T) == 8 ? NR <= 2 : NR == 1; }
+template <typename T, int NR> constexpr int vec_depth() { return 8; }
+template <typename T, int NR> constexpr int vec_xs_bytes() { return sizeof(T) == 8 && NR >= 4 ? 8192 : 4096; }
+template <typename T, int NR> constexpr int vp_depth() { return sizeof(T) == 8 && NR == 2 ? 8 : 4; }
+template <typename T, int NR> constexpr int vp_xs_bytes() { return sizeof(T) == 8 && NR == 2 ? 8192 : 4096; }
 
 template <typename T, int NR, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
   extern __shared__ double s_mom[];
-  constexpr int XCAP = kXsBytes / sizeof(T);
-  constexpr int U = NR <= 2 ? 4 : 2;
-  __shared__ T xs_all[kWaves * XCAP];
+  constexpr int XCAP = vec_xs_bytes<T, NR>() / sizeof(T);
+  constexpr int U = vec_depth<T, NR>();
+  __shared__ __align__(16) T xs_all[kWaves * XCAP];
   const int wg = xcd_remap(blockIdx.x, gridDim.x);
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
@@ -247,7 +307,10 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
 #pragma unroll
         for (int u = 0; u < U; ++u) a[u] = buf_load_nt<T>(vr, lo + u * stepb);
         wave_lds_sync();  // previous chunk fully consumed
-        stage_x<T, NR, (NR <= 2 ? 4 : 2)>(xs, cxrow, P.X, P.ldx, c0, nc, kc, kn, lane);
+        if (NR > 1 && nc == NR && P.xrow16)
+          stage_x_rows<T, NR>(xs, cxrow, P.X, P.ldx, c0, kc, kn, lane);
+        else
+          stage_x<T, NR, (NR <= 2 ? 4 : 2)>(xs, cxrow, P.X, P.ldx, c0, nc, kc, kn, lane);
         for (int e = kn * NR + lane; e < ngrp * G * U * NR; e += 64) xs[e] = T(0);
         wave_lds_sync();
         if (g < G) {
@@ -286,6 +349,154 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
         for (int c = 0; c < NR; ++c) {
           if (c < nc) {
             T y = T(P.alpha) * acc[c];
+            if (P.beta != 0.0) y = fma(T(P.beta), yi[c], y);
+            yo[c] = y;
+            if (MOM) mom[c] = (double)P.R[r * P.ldr + c0 + c] * (double)y;
+          }
+        }
+      }
+      if (MOM) {
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          const double t = wave_sum(mom[c]);
+          if (lane == 0 && c < nc) s_mom[w * P.nrhs + c0 + c] += t;
+        }
+      }
+    }
+  }
+  mom_flush<MOM>(s_mom, P.nrhs, wg, P.mom);
+}
+
+// ---------------------------------------------------------------------------
+// vector-FMA product with 16-byte value loads
+// ---------------------------------------------------------------------------
+// A step covers C panel columns (C*b values, contiguous in the column-major
+// panel); lane l loads the E = 16/sizeof(T) consecutive values E*l .. E*l+E-1
+// of the step with one 16-byte load.  C is the largest multiple of E with
+// C*b <= 64*E, so the step length is a multiple of b and every lane keeps
+// the same E panel rows in every step; lanes l and l + b hold the same rows.
+// X rows are staged in LDS as in the kernel above.
+template <typename T, int NR, bool MOM>
+__global__ void __launch_bounds__(kThreads) k_spmm_vp(FwdParams<T> P) {
+  extern __shared__ double s_mom[];
+  constexpr int E = 16 / (int)sizeof(T);
+  constexpr int XCAP = vp_xs_bytes<T, NR>() / sizeof(T);
+  constexpr int U = vp_depth<T, NR>();
+  __shared__ __align__(16) T xs_all[kWaves * XCAP];
+  const int wg = xcd_remap(blockIdx.x, gridDim.x);
+  const int w = wave_id();
+  const int lane = threadIdx.x & 63;
+  const int row = wg * kWaves + w;
+  T *xs = xs_all + w * XCAP;
+  mom_init<MOM>(s_mom, P.nrhs);
+  if (row < P.nrows) {
+    const RowDesc rd = P.rows[row];
+    const int b = rd.b, K = rd.K;
+    // columns per step (a multiple of E), capped so a staged chunk holds U steps
+    constexpr int CMAX = XCAP / (NR * U) / E * E;
+    static_assert(CMAX >= E, "LDS staging buffer too small");
+    const int C = min((64 * E / b) / E * E, CMAX);
+    const int NL = C * b / E;  // active lanes
+    int cj[E], rj[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = E * lane + j;
+      cj[j] = e / b;
+      rj[j] = e - cj[j] * b;
+    }
+    const int ccap = (XCAP / NR) / (C * U) * (C * U);
+    const int32_t *__restrict__ cxrow = P.colx + rd.cbase;
+    for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
+      const int nc = min(NR, P.nrhs - c0);
+      T acc[E][NR];
+#pragma unroll
+      for (int j = 0; j < E; ++j)
+#pragma unroll
+        for (int c = 0; c < NR; ++c) acc[j][c] = T(0);
+      for (int kc = 0; kc < K; kc += ccap) {
+        const int kn = min(ccap, K - kc);
+        const int ngrp = (kn + C * U - 1) / (C * U);
+        const __amdgpu_buffer_rsrc_t vr =
+            panel_rsrc(P.vals + rd.vbase + (int64_t)kc * b, (uint32_t)(kn * b * sizeof(T)));
+        const uint32_t lo = (uint32_t)lane * 16;
+        const uint32_t stepb = (uint32_t)(C * b) * sizeof(T);
+        v4u32 a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          a[u] = __builtin_bit_cast(v4u32, __builtin_amdgcn_raw_buffer_load_b128(vr, lo + u * stepb, 0, 2));
+        wave_lds_sync();
+        if (NR > 1 && nc == NR && P.xrow16)
+          stage_x_rows<T, NR>(xs, cxrow, P.X, P.ldx, c0, kc, kn, lane);
+        else
+          stage_x<T, NR, (NR <= 2 ? 4 : 2)>(xs, cxrow, P.X, P.ldx, c0, nc, kc, kn, lane);
+        for (int e = kn * NR + lane; e < ngrp * C * U * NR; e += 64) xs[e] = T(0);
+        wave_lds_sync();
+        if (lane < NL) {
+          for (int q = 0; q < ngrp; ++q) {
+            const int s = q * U;
+            v4u32 an[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+              an[u] = __builtin_bit_cast(
+                  v4u32, __builtin_amdgcn_raw_buffer_load_b128(vr, lo + (s + U + u) * stepb, 0, 2));
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              const T *av = reinterpret_cast<const T *>(&a[u]);
+#pragma unroll
+              for (int j = 0; j < E; ++j) {
+                const T *xp = xs + ((s + u) * C + cj[j]) * NR;
+#pragma unroll
+                for (int c = 0; c < NR; ++c) acc[j][c] = fma(av[j], xp[c], acc[j][c]);
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) a[u] = an[u];
+          }
+        }
+      }
+      // lanes l and l + b hold the same rows: tree over the C/E groups
+      const int ng = C / E;
+      const int g = lane / b;
+      for (int st = 1; st < ng; st <<= 1) {
+#pragma unroll
+        for (int j = 0; j < E; ++j)
+#pragma unroll
+          for (int c = 0; c < NR; ++c) {
+            const T o = __shfl_down(acc[j][c], st * b, 64);
+            if ((g & (2 * st - 1)) == 0 && g + st < ng) acc[j][c] += o;
+          }
+      }
+      // lanes < b now hold values E*l + j of the first E*b; row p collects
+      // values p + t*b, t < E (lane (p + t*b) / E, slot (p + t*b) % E)
+      T ysum[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) ysum[c] = T(0);
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        const int e = (lane < b ? lane : 0) + t * b;
+        const int sl = e / E, sj = e - sl * E;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          T v = T(0);
+#pragma unroll
+          for (int j = 0; j < E; ++j) {
+            const T o = __shfl(acc[j][c], sl, 64);
+            v = sj == j ? o : v;
+          }
+          ysum[c] += v;
+        }
+      }
+      double mom[NR];
+#pragma unroll
+      for (int c = 0; c < NR; ++c) mom[c] = 0.0;
+      if (lane < b) {
+        const int64_t r = (int64_t)rd.yrow + lane;
+        T *yo = P.Yout + r * P.ldy + c0;
+        const T *yi = P.Yin + r * P.ldyin + c0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          if (c < nc) {
+            T y = T(P.alpha) * ysum[c];
             if (P.beta != 0.0) y = fma(T(P.beta), yi[c], y);
             yo[c] = y;
             if (MOM) mom[c] = (double)P.R[r * P.ldr + c0 + c] * (double)y;
@@ -969,11 +1180,20 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const double *partial, int6
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T, int NR>
-hipError_t launch_vec_nr(const FwdParams<T> &p, hipStream_t s, dim3 grid, size_t shm) {
-  if (p.mom)
-    hipLaunchKernelGGL((k_spmm_vec<T, NR, true>), grid, dim3(kThreads), shm, s, p);
-  else
-    hipLaunchKernelGGL((k_spmm_vec<T, NR, false>), grid, dim3(kThreads), 0, s, p);
+hipError_t launch_vec_nr(const FwdParams<T> &p0, hipStream_t s, dim3 grid, size_t shm) {
+  FwdParams<T> p = p0;
+  p.xrow16 = (reinterpret_cast<uintptr_t>(p.X) % 16 == 0 && (p.ldx * sizeof(T)) % 16 == 0) ? 1 : 0;
+  if constexpr (use_vp<T, NR>()) {
+    if (p.mom)
+      hipLaunchKernelGGL((k_spmm_vp<T, NR, true>), grid, dim3(kThreads), shm, s, p);
+    else
+      hipLaunchKernelGGL((k_spmm_vp<T, NR, false>), grid, dim3(kThreads), 0, s, p);
+  } else {
+    if (p.mom)
+      hipLaunchKernelGGL((k_spmm_vec<T, NR, true>), grid, dim3(kThreads), shm, s, p);
+    else
+      hipLaunchKernelGGL((k_spmm_vec<T, NR, false>), grid, dim3(kThreads), 0, s, p);
+  }
   return hipGetLastError();
 }
 

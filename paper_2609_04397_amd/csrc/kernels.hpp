@@ -25,6 +25,7 @@ struct FwdParams {
   const T *X;
   int64_t ldx;
   int64_t xrows;        // rows of X (columns of the operator)
+  int32_t xrow16;       // set by the launcher: X rows start on 16-byte boundaries
   const T *Yin;
   int64_t ldyin;
   T *Yout;

@@ -203,11 +203,24 @@ def test_bitwise_reproducible():
         assert np.array_equal(host(A.sddmm(X, X)), host(A.sddmm(X, X)))
 
 
-def test_vec_tiles_agree_with_oracle():
-    op, vec = make_config("C1", scale=0.2, nrhs=8)
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vec_tiles_agree_with_oracle(prec):
+    """Every pass width of the vector kernel, full and ragged last passes,
+    and X rows that do / do not start on 16-byte boundaries (the staging of
+    whole row pieces applies only to the former)."""
+    op, vec = make_config("C1", scale=0.2, nrhs=12)
     X = vec["X"]
-    ref = oracle.spmm(op, X)
-    scale = oracle.abs_product(op, X)
-    for tile in (1, 2, 4, 8):
-        A = Matrix.from_operator(op, path="vec", nrhs_tile=tile)
-        check(host(A.spmm(dev(X, "fp64"))), ref, "fp64", scale, "tile %d" % tile)
+    Xr = rounded(X, prec)
+    for nrhs in (8, 12):
+        ref = oracle.spmm(op, Xr[:, :nrhs])
+        scale = oracle.abs_product(op, Xr[:, :nrhs]) if prec == "fp64" else None
+        for tile in (1, 2, 4, 8):
+            print("case vec tile", prec, nrhs, tile, flush=True)
+            A = Matrix.from_operator(op, prec=prec, path="vec", nrhs_tile=tile)
+            check(host(A.spmm(dev(X[:, :nrhs], prec))), ref, prec, scale, "tile %d nrhs %d" % (tile, nrhs))
+            for ld, off in ((16, 0), (17, 1), (18, 2)):
+                big = torch.zeros((op.N, ld), dtype=DT[prec], device="cuda")
+                big[:, off:off + nrhs] = dev(X[:, :nrhs], prec)
+                got = host(A.spmm(big[:, off:off + nrhs]))
+                check(got, ref, prec, scale, "tile %d nrhs %d ld %d off %d" % (tile, nrhs, ld, off))
+            A.close()
