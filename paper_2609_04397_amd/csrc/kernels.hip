@@ -256,11 +256,11 @@ __device__ __forceinline__ void stage_x_rows(T *xs, const int32_t *__restrict__ 
 // widths use 16-byte value loads (the kernel after this one), the value
 // loads in flight per lane (steps of look-ahead) and the LDS staging per
 // wave in bytes.
-template <typename T, int NR> constexpr bool use_vp() { return sizeof(T) == 8 ? NR <= 2 : NR == 1; }
+template <typename T, int NR> constexpr bool use_vp() { return sizeof(T) == 8 ? NR <= 4 : NR == 1; }
 template <typename T, int NR> constexpr int vec_depth() { return 8; }
 template <typename T, int NR> constexpr int vec_xs_bytes() { return sizeof(T) == 8 && NR >= 4 ? 8192 : 4096; }
-template <typename T, int NR> constexpr int vp_depth() { return sizeof(T) == 8 && NR == 2 ? 8 : 4; }
-template <typename T, int NR> constexpr int vp_xs_bytes() { return sizeof(T) == 8 && NR == 2 ? 8192 : 4096; }
+template <typename T, int NR> constexpr int vp_depth() { return sizeof(T) == 8 && NR >= 2 ? 8 : 4; }
+template <typename T, int NR> constexpr int vp_xs_bytes() { return sizeof(T) == 8 && NR >= 2 ? 8192 : 4096; }
 
 template <typename T, int NR, bool MOM>
 __global__ void __launch_bounds__(kThreads) k_spmm_vec(FwdParams<T> P) {
@@ -1046,10 +1046,10 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
 // For block row i the result is the b_i x K_i panel dY_i Xg_i^T, Xg_i the X
 // rows of the panel's columns: a 16 x 16 output tile per MFMA chain with
 // M = panel rows, N = 16 panel columns, K = right-hand sides.  Lane (m, kq)
-// holds right-hand sides 8kq..8kq+7 of each 32-wide chunk contiguously for
-// both operands (the contraction order inside a chunk is permuted, the sum is
-// the same).  Each output goes to graph order through colg = (graph offset of
-// the column's block + q) << 7 | b_j.
+// holds 8 of the right-hand sides of each 32-wide chunk, the same ones for
+// both operands (the contraction order inside a chunk is permuted, the sum
+// is the same).  Each output goes to graph order through colg = (graph
+// offset of the column's block + q) << 7 | b_j.
 template <typename T, int NCH>
 __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   using V = typename Frag<T>::type;
@@ -1068,17 +1068,24 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
   for (int mt = 0; mt * 16 < b; ++mt) {
     const int p = mt * 16 + m;
     const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
-    auto ldrun = [&](const T *src, int cb, bool ok, T *dst) {
-      // 8 consecutive right-hand sides starting at cb (zero outside)
-      if (cb + 8 <= P.nrhs) {
+    // lane group kq holds 8 right-hand sides of each 32-wide chunk, the same
+    // ones for both operands: FP64 takes c = 32 ch + 8 l + 2 kq + e (l < 4,
+    // e < 2), so the four lane groups of one 16-byte load read 64 contiguous
+    // bytes of a row; FP32 takes c = 32 ch + 8 kq + s (two 16-byte loads)
+    constexpr bool PAIR = sizeof(T) == 8;
+    const int kofs = PAIR ? 2 * kq : 8 * kq;
+    auto ldrun = [&](const T *src, int ch, bool ok, T *dst) {
+      const int cb = ch * 32 + kofs;
+      auto rhs = [&](int s) { return PAIR ? cb + 8 * (s >> 1) + (s & 1) : cb + s; };
+      if (ch * 32 + 32 <= P.nrhs) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) dst[s] = src[cb + s];
+        for (int s = 0; s < 8; ++s) dst[s] = src[rhs(s)];
 #pragma unroll
         for (int s = 0; s < 8; ++s) dst[s] = ok ? dst[s] : T(0);
       } else {
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const int c = cb + s;
+          const int c = rhs(s);
           const T v = src[min(c, P.nrhs - 1)];
           dst[s] = (ok && c < P.nrhs) ? v : T(0);
         }
@@ -1087,7 +1094,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
     // A fragments (dY rows) of the first NCH 32-wide chunks stay in registers
     T af[NCH][8];
 #pragma unroll
-    for (int ch = 0; ch < NCH; ++ch) ldrun(dyrow, ch * 32 + kq * 8, p < b && ch < nch, af[ch]);
+    for (int ch = 0; ch < NCH; ++ch) ldrun(dyrow, ch, p < b && ch < nch, af[ch]);
     // one 16-column tile: B fragments of chunk 0/1 and the output map
     struct Tile {
       T bv[NCH][8];
@@ -1102,7 +1109,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
       tl.xrow = P.X + (int64_t)cx[kk] * P.ldx;
       tl.g = cg[kk];
 #pragma unroll
-      for (int ch = 0; ch < NCH; ++ch) ldrun(tl.xrow, ch * 32 + kq * 8, tl.kin && ch < nch, tl.bv[ch]);
+      for (int ch = 0; ch < NCH; ++ch) ldrun(tl.xrow, ch, tl.kin && ch < nch, tl.bv[ch]);
     };
     // one tile's products, split over two independent accumulator chains
     auto do_tile = [&](const Tile &tl) {
@@ -1116,8 +1123,8 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
         }
       for (int ch = NCH; ch < nch; ++ch) {
         T av[8], bv[8];
-        ldrun(dyrow, ch * 32 + kq * 8, p < b, av);
-        ldrun(tl.xrow, ch * 32 + kq * 8, tl.kin, bv);
+        ldrun(dyrow, ch, p < b, av);
+        ldrun(tl.xrow, ch, tl.kin, bv);
 #pragma unroll
         for (int s = 0; s < 8; s += 2) {
           acc0 = mfma(av[s], bv[s], acc0);
