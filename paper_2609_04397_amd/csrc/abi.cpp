@@ -345,6 +345,11 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
       const size_t es = prec == VBCSR_FP64 ? 8 : 4;
       char *p = nullptr;
       if ((rc = alloc_into(A, &p, es * (size_t)P.n_values))) return bail(rc);
+      // the padding after each panel must read as zero
+      if (P.n_values) {
+        hipError_t e = hipMemsetAsync(p, 0, es * (size_t)P.n_values, s);
+        if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
+      }
       D.vals = p;
     }
   }

@@ -29,6 +29,10 @@ struct RowDesc {
 };
 static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 
+// Value pages: every panel starts at a multiple of this many values; the
+// gap after a panel holds zeros.
+constexpr int64_t kPanelAlign = 4;
+
 struct DirPlan {
   std::vector<RowDesc> rows;     // one per atom, atom order
   std::vector<int32_t> colx;     // per panel column: scalar row of the input vector

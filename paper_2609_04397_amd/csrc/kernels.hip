@@ -416,8 +416,10 @@ __global__ void __launch_bounds__(kThreads) k_spmm_vp(FwdParams<T> P) {
       for (int kc = 0; kc < K; kc += ccap) {
         const int kn = min(ccap, K - kc);
         const int ngrp = (kn + C * U - 1) / (C * U);
-        const __amdgpu_buffer_rsrc_t vr =
-            panel_rsrc(P.vals + rd.vbase + (int64_t)kc * b, (uint32_t)(kn * b * sizeof(T)));
+        // the chunk's values rounded up to whole 16-byte loads: the pages
+        // pad every panel with zeros to a multiple of 4 values
+        const __amdgpu_buffer_rsrc_t vr = panel_rsrc(P.vals + rd.vbase + (int64_t)kc * b,
+                                                     (uint32_t)((kn * b + E - 1) / E * E * sizeof(T)));
         const uint32_t lo = (uint32_t)lane * 16;
         const uint32_t stepb = (uint32_t)(C * b) * sizeof(T);
         v4u32 a[U];

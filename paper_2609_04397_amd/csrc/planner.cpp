@@ -118,7 +118,9 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
       }
       k0 += b[c];
     }
-    vbase += (int64_t)h * K;
+    // panels start on 4-value boundaries (zero padding), so a 16-byte load
+    // of values never mixes two panels
+    vbase += ((int64_t)h * K + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
     cbase += K;
     vbase16 += (int64_t)h * ((K + 7) / 8 * 8);
   }

@@ -62,7 +62,8 @@ def test_planner_shape_classes_match_recount(lib):
     bj = op.b[op.col_idx]
     u, c = np.unique(np.stack([bi, bj], 1), axis=0, return_counts=True)
     assert np.array_equal(shapes[:, :2], u) and np.array_equal(shapes[:, 2], c)
-    assert pv == op.nnz
+    # every panel padded to a multiple of 4 values
+    assert op.nnz <= pv < op.nnz + 4 * op.n
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
@@ -77,8 +78,14 @@ def test_page_maps_are_bijections(lib, seed):
         order = np.argsort(pos)
         starts = pos[order]
         ends = starts + sizes[order]
-        assert starts[0] == 0 and ends[-1] == pv
-        assert np.array_equal(starts[1:], ends[:-1])  # blocks tile the pages exactly
+        assert starts[0] == 0
+        if pos is fwd:  # page_values counts the forward pages
+            assert ends[-1] <= pv < ends[-1] + 4
+        gaps = starts[1:] - ends[:-1]
+        # blocks tile the pages except for < 4 values of padding after a
+        # panel, so that every panel starts on a multiple of 4
+        assert np.all((gaps >= 0) & (gaps < 4))
+        assert np.all(starts[1:][gaps > 0] % 4 == 0)
 
 
 def test_forward_pages_group_rows_and_shapes(lib):

@@ -140,6 +140,45 @@ def test_x_rows_beyond_2gib(prec):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("prec,path,nrhs", [("fp64", "vec", 1), ("fp64", "vec", 2), ("fp64", "vec", 4),
+                                            ("fp64", "vec", 8), ("fp32", "vec", 1), ("fp32", "vec", 2),
+                                            ("fp64", "mfma", 16), ("fp32", "mfma", 32),
+                                            ("bf16x3", "auto", 64)])
+def test_nonfinite_values_stay_in_their_rows(prec, path, nrhs):
+    """Inf in the blocks of a few block rows reaches exactly the outputs those
+    blocks feed; neighbouring panels (odd lengths, so their last value loads
+    end next to an Inf panel) stay finite and match the oracle."""
+    op = random_pattern(21, 30, bset=(1, 3, 5, 13), density=0.25, empty_rows=2)
+    bad = np.array([3, 10, 17])
+    rows = op.block_rows
+    vmask = np.repeat(np.isin(rows, bad), np.diff(op.block_base))
+    vals = op.values.copy()
+    vals[vmask] = np.inf
+    clean = op.values.copy()
+    clean[vmask] = 0.0
+    from workloads.core import Operator
+    op0 = Operator(op.name, op.b, op.row_ptr, op.col_idx, clean, op.dist)
+    A = Matrix.from_operator(op, prec=prec, values=vals, path=path)
+    X = np.random.default_rng(9).standard_normal((op.N, nrhs))
+    Xr = rounded(X, prec)
+    off = op.off
+    fwd_bad = np.isin(np.arange(op.n), bad)
+    adj_bad = np.zeros(op.n, bool)
+    adj_bad[op.col_idx[np.isin(rows, bad)]] = True
+    for transpose, atom_bad in ((False, fwd_bad), (True, adj_bad)):
+        print("case nonfinite", prec, path, nrhs, transpose, flush=True)
+        got = host(A.spmm(dev(X, prec), transpose=transpose))
+        good = np.repeat(~atom_bad, np.diff(off))
+        ref = (oracle.spmm_t if transpose else oracle.spmm)(op0, Xr)
+        assert np.all(np.isfinite(got[good]))
+        # an output fed by an Inf block is not finite
+        fed = np.repeat(atom_bad & (np.bincount(rows if not transpose else op.col_idx,
+                                                minlength=op.n) > 0), np.diff(off))
+        assert not np.isfinite(got[fed]).any()
+        check(got[good], ref[good], prec, label="nonfinite %s %s %d T=%s" % (prec, path, nrhs, transpose))
+    A.close()
+
+
 def test_argument_errors_on_device():
     from paper_2609_04397_amd import _lib, VbcsrError
     import ctypes
