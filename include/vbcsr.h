@@ -57,17 +57,29 @@ enum {
 };
 
 enum { VBCSR_PATH_AUTO = 0, VBCSR_PATH_VEC = 1, VBCSR_PATH_MFMA = 2 };
+enum { VBCSR_ORDER_AUTO = 0, VBCSR_ORDER_ATOM = 1, VBCSR_ORDER_RCM = 2 };
 
 /* Planner options; zero fields mean "choose automatically".
  *   path:        VBCSR_PATH_* -- force the vector-FMA or the matrix-core
  *                kernel family for FP64/FP32 (BF16X3 always uses matrix cores);
  *                the environment variable VBCSR_PATH={auto,vec,mfma} overrides.
  *   nrhs_tile:   columns per pass of the vector kernel (1, 2, 4 or 8).
- *   rows_per_wg: reserved, must be 0.                                          */
+ *   rows_per_wg: reserved, must be 0.
+ *   row_order:   VBCSR_ORDER_* -- order in which the device lays out and
+ *                processes the block rows (and block columns, for the
+ *                adjoint): atom order, or reverse Cuthill-McKee of the
+ *                symmetrised block graph, so that consecutive panels share
+ *                input rows in cache.  Results are the same up to rounding
+ *                (each output still has one writer summing its row in panel
+ *                order); moments of the Chebyshev helpers are reduced in the
+ *                processing order.  AUTO takes RCM when it at least halves
+ *                the mean processing distance between the two atoms of a
+ *                block, else atom order.                                      */
 typedef struct {
   int32_t rows_per_wg;
   int32_t nrhs_tile;
   int32_t path;
+  int32_t row_order;
 } vbcsr_plan_opts;
 
 /* Largest block size (orbitals per atom) this build accepts. */
@@ -205,13 +217,14 @@ int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_va
  *   fwd_pos      out [nnzb] or NULL: offset, in the forward value pages, of the
  *                first value of every graph-order block
  *   tr_pos       out [nnzb] or NULL: the same for the transposed pages
- *   page_values  out or NULL: number of values in each set of pages
+ *   page_values  out or NULL: number of values in the forward pages
+ *   opts         may be NULL (row_order is the only field used)
  * Errors: as vbcsr_create, minus device errors.
  */
 int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
                     const int32_t *col_idx, int64_t n_values, int32_t *n_shapes,
                     int32_t *shapes, int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos,
-                    int64_t *page_values);
+                    int64_t *page_values, const vbcsr_plan_opts *opts);
 
 /* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
 void vbcsr_destroy(vbcsr_mat *A);

@@ -23,6 +23,7 @@ CODE_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EDUP", -4: "ENOMEM", -5:
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PATH = {"auto": 0, "vec": 1, "mfma": 2}
+ORDER = {"auto": 0, "atom": 1, "rcm": 2}
 
 # Every symbol declared in include/vbcsr.h, with (restype, argtypes).
 _p = ctypes.c_void_p
@@ -34,7 +35,7 @@ _int = ctypes.c_int
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("rows_per_wg", ctypes.c_int32), ("nrhs_tile", ctypes.c_int32),
-                ("path", ctypes.c_int32)]
+                ("path", ctypes.c_int32), ("row_order", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -50,7 +51,7 @@ SIGNATURES = {
     "vbcsr_info": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                           ctypes.POINTER(_i32)]),
     "vbcsr_plan_host": (_int, [_i32, _p, _p, _p, _i64, ctypes.POINTER(_i32), _p, _i32, _p, _p,
-                               ctypes.POINTER(_i64)]),
+                               ctypes.POINTER(_i64), ctypes.POINTER(PlanOpts)]),
     "vbcsr_destroy": (None, [_p]),
     "vbcsr_last_error": (ctypes.c_char_p, []),
 }

@@ -251,11 +251,13 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
 }
 
 int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                 int64_t n_values, HostPlan &plan) {
+                 int64_t n_values, const vbcsr_plan_opts *opts, HostPlan &plan) {
   std::string err;
+  if (opts && (opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
+    return fail(VBCSR_EINVAL, "row_order must be one of VBCSR_ORDER_*");
   int rc = validate_graph(n, b, row_ptr, col_idx, n_values, err);
   if (rc) return fail(rc, err);
-  build_plan(n, b, row_ptr, col_idx, plan);
+  build_plan(n, b, row_ptr, col_idx, opts ? opts->row_order : VBCSR_ORDER_AUTO, plan);
   return VBCSR_OK;
 }
 
@@ -267,9 +269,10 @@ const char *vbcsr_last_error(void) { return g_last_error.c_str(); }
 
 int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
                     const int32_t *col_idx, int64_t n_values, int32_t *n_shapes, int32_t *shapes,
-                    int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values) {
+                    int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values,
+                    const vbcsr_plan_opts *opts) {
   HostPlan plan;
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, plan);
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
   if (rc) return rc;
   if (n_shapes) *n_shapes = (int32_t)plan.shapes.size();
   if (shapes)
@@ -291,7 +294,7 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA))
     return fail(VBCSR_EINVAL, "invalid plan options");
   HostPlan plan;
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, plan);
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
   if (rc) return rc;
 
   hipStream_t s = static_cast<hipStream_t>(stream);

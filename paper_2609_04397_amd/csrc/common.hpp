@@ -34,14 +34,14 @@ static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 constexpr int64_t kPanelAlign = 4;
 
 struct DirPlan {
-  std::vector<RowDesc> rows;     // one per atom, atom order
+  std::vector<RowDesc> rows;     // one per atom, in processing order
   std::vector<int32_t> colx;     // per panel column: scalar row of the input vector
   std::vector<int64_t> colg;     // forward only, per panel column: (graph offset of the
                                  // column's block + q) << 7 | b_j (block-sampled product)
   std::vector<int64_t> blk_pos;  // per graph block: page offset of its first value
   std::vector<int32_t> blk_k0;   // per graph block: first panel column
-  std::vector<int32_t> blk_prow; // per graph block: atom whose panel holds it
-  std::vector<int64_t> vbase16;  // per atom: offset in the BF16 pages (8-column groups)
+  std::vector<int32_t> blk_prow; // per graph block: index (processing order) of its panel
+  std::vector<int64_t> vbase16;  // per panel (processing order): offset in the BF16 pages
   int64_t n_values = 0;          // values in the pages
   int64_t n_values16 = 0;        // values in each BF16 page (panels padded to 8 columns)
   int64_t n_cols = 0;            // entries of the column table
@@ -64,6 +64,6 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 
 // Build both directions of the plan (assumes validate_graph passed).
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                HostPlan &plan);
+                int32_t row_order, HostPlan &plan);
 
 }  // namespace vbcsr

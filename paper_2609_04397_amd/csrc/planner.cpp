@@ -4,6 +4,7 @@
 // in a shape-specific buffer; here the buffer of a shape class inside a block
 // row is one contiguous run of the row's panel).
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -81,7 +82,8 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 // together with the atom that indexes their panel columns.
 static void layout_direction(int32_t n, const int32_t *b, const std::vector<int64_t> &off,
                              const std::vector<std::vector<std::pair<int32_t, int64_t>>> &members,
-                             int64_t nnzb, const std::vector<int64_t> *gbase, DirPlan &d) {
+                             int64_t nnzb, const std::vector<int64_t> *gbase,
+                             const std::vector<int32_t> &order, DirPlan &d) {
   int64_t total_cols = 0;
   for (int32_t r = 0; r < n; ++r)
     for (const auto &m : members[r]) total_cols += b[m.first];
@@ -93,7 +95,9 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
   d.blk_k0.assign(nnzb, 0);
   d.blk_prow.assign(nnzb, 0);
   int64_t vbase = 0, cbase = 0, vbase16 = 0;
-  for (int32_t r = 0; r < n; ++r) {
+  // panels are laid out and processed in `order` (panel pi holds atom r)
+  for (int32_t pi = 0; pi < n; ++pi) {
+    const int32_t r = order[pi];
     const int32_t h = b[r];
     int32_t K = 0;
     for (const auto &m : members[r]) K += b[m.first];
@@ -103,15 +107,15 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
     rd.K = K;
     rd.yrow = (int32_t)off[r];
     rd.b = h;
-    d.rows[r] = rd;
-    d.vbase16[r] = vbase16;
+    d.rows[pi] = rd;
+    d.vbase16[pi] = vbase16;
     int32_t k0 = 0;
     for (const auto &m : members[r]) {
       const int32_t c = m.first;     // atom indexing the block's panel columns
       const int64_t k = m.second;    // graph block index
       d.blk_pos[k] = vbase + (int64_t)k0 * h;
       d.blk_k0[k] = k0;
-      d.blk_prow[k] = r;
+      d.blk_prow[k] = pi;
       for (int32_t q = 0; q < b[c]; ++q) {
         d.colx.push_back((int32_t)(off[c] + q));
         if (gbase) d.colg.push_back((((*gbase)[k] + q) << 7) | b[c]);
@@ -129,8 +133,60 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
   d.n_values16 = vbase16;
 }
 
+// Reverse Cuthill-McKee order of the symmetrised block graph: breadth-first
+// from a lowest-degree unvisited atom of each component, neighbours in
+// ascending degree, the whole sequence reversed.  Panels processed in this
+// order are graph neighbours of the panels processed just before them, so
+// the input rows they gather are still in the XCD's L2.
+static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const int32_t *col_idx) {
+  std::vector<int64_t> deg((size_t)n, 0);
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (col_idx[k] != i) {
+        ++deg[i];
+        ++deg[col_idx[k]];
+      }
+  std::vector<int64_t> ap((size_t)n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) ap[i + 1] = ap[i] + deg[i];
+  std::vector<int32_t> adj((size_t)ap[n]);
+  std::vector<int64_t> fill(ap.begin(), ap.end() - 1);
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      const int32_t j = col_idx[k];
+      if (j == i) continue;
+      adj[fill[i]++] = j;
+      adj[fill[j]++] = i;
+    }
+  auto by_degree = [&](int32_t x, int32_t y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; };
+  for (int32_t i = 0; i < n; ++i) std::sort(adj.begin() + ap[i], adj.begin() + ap[i + 1], by_degree);
+  std::vector<int32_t> starts((size_t)n);
+  std::iota(starts.begin(), starts.end(), 0);
+  std::sort(starts.begin(), starts.end(), by_degree);
+  std::vector<char> seen((size_t)n, 0);
+  std::vector<int32_t> order;
+  order.reserve((size_t)n);
+  for (int32_t s0 : starts) {
+    if (seen[s0]) continue;
+    seen[s0] = 1;
+    size_t head = order.size();
+    order.push_back(s0);
+    while (head < order.size()) {
+      const int32_t v = order[head++];
+      for (int64_t e = ap[v]; e < ap[v + 1]; ++e) {
+        const int32_t u = adj[e];
+        if (!seen[u]) {
+          seen[u] = 1;
+          order.push_back(u);
+        }
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                HostPlan &plan) {
+                int32_t row_order, HostPlan &plan) {
   plan.n = n;
   plan.off.assign((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) plan.off[i + 1] = plan.off[i] + b[i];
@@ -150,6 +206,27 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   plan.nnz = plan.gbase[nnzb];
   plan.shapes.clear();
   for (const auto &kv : shape_count) plan.shapes.push_back({kv.first.first, kv.first.second, kv.second});
+  std::vector<int32_t> order((size_t)n);
+  std::iota(order.begin(), order.end(), 0);
+  if (row_order != VBCSR_ORDER_ATOM) {
+    std::vector<int32_t> rcm = rcm_order(n, row_ptr, col_idx);
+    // AUTO keeps the caller's order unless RCM at least halves the mean
+    // distance, in processing order, between the two atoms of a block
+    // (a lattice or a spatially sorted input already has locality)
+    bool take = row_order == VBCSR_ORDER_RCM;
+    if (!take && nnzb > 0) {
+      std::vector<int32_t> pos((size_t)n);
+      for (int32_t t = 0; t < n; ++t) pos[rcm[t]] = t;
+      double d_atom = 0.0, d_rcm = 0.0;
+      for (int32_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+          d_atom += std::abs((double)i - (double)col_idx[k]);
+          d_rcm += std::abs((double)pos[i] - (double)pos[col_idx[k]]);
+        }
+      take = 2.0 * d_rcm <= d_atom;
+    }
+    if (take) order.swap(rcm);
+  }
 
   // forward: panel i holds the blocks of block row i, ordered by (b_j, j)
   std::vector<std::vector<std::pair<int32_t, int64_t>>> members((size_t)n);
@@ -162,7 +239,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
       return x.first < y.first;
     });
   }
-  layout_direction(n, b, plan.off, members, nnzb, &plan.gbase, plan.fwd);
+  layout_direction(n, b, plan.off, members, nnzb, &plan.gbase, order, plan.fwd);
 
   // transposed: panel j holds the blocks (i, j) of block column j, ordered by (b_i, i)
   for (auto &m : members) m.clear();
@@ -174,7 +251,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
       if (b[x.first] != b[y.first]) return b[x.first] < b[y.first];
       return x.first < y.first;
     });
-  layout_direction(n, b, plan.off, members, nnzb, nullptr, plan.tr);
+  layout_direction(n, b, plan.off, members, nnzb, nullptr, order, plan.tr);
 }
 
 }  // namespace vbcsr

@@ -41,7 +41,7 @@ class Matrix:
     _stamps = 0  # bumped by every value upload; lets autograd detect repacks
 
     def __init__(self, block_sizes, row_ptr, col_idx, values=None, prec: str = "fp64",
-                 path: str = "auto", nrhs_tile: int = 0):
+                 path: str = "auto", nrhs_tile: int = 0, row_order: str = "auto"):
         lib = _lib.load()
         if prec not in _lib.PREC:
             raise ValueError("prec must be one of %s" % list(_lib.PREC))
@@ -57,7 +57,7 @@ class Matrix:
                    * b[ci].astype(np.int64)).sum()) if ci.size else 0
         self.n_values = nnz
         self.N = int(b.astype(np.int64).sum())
-        opts = _lib.PlanOpts(0, int(nrhs_tile), _lib.PATH[path])
+        opts = _lib.PlanOpts(0, int(nrhs_tile), _lib.PATH[path], _lib.ORDER[row_order])
         host_vals = None
         dev_vals = None
         if isinstance(values, torch.Tensor) and values.is_cuda:

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(_lib.SIGNATURES), "ctypes table and header disagree"
 
 
-def _plan(lib, b, rp, ci, nval, fwd=None, tr=None, max_shapes=256):
+def _plan(lib, b, rp, ci, nval, fwd=None, tr=None, max_shapes=256, order="atom"):
     b = np.ascontiguousarray(b, np.int32)
     rp = np.ascontiguousarray(rp, np.int64)
     ci = np.ascontiguousarray(ci, np.int32)
@@ -50,7 +50,8 @@ def _plan(lib, b, rp, ci, nval, fwd=None, tr=None, max_shapes=256):
     rc = lib.vbcsr_plan_host(b.size, b.ctypes.data, rp.ctypes.data, ci.ctypes.data if ci.size else None,
                              nval, ctypes.byref(ns), shapes.ctypes.data, max_shapes,
                              fwd.ctypes.data if fwd is not None else None,
-                             tr.ctypes.data if tr is not None else None, ctypes.byref(pv))
+                             tr.ctypes.data if tr is not None else None, ctypes.byref(pv),
+                             ctypes.byref(_lib.PlanOpts(0, 0, 0, _lib.ORDER[order])))
     return rc, ns.value, shapes[:3 * ns.value].reshape(-1, 3), pv.value
 
 
@@ -164,6 +165,53 @@ def test_panel_size_limit(lib):
     ci = np.arange(n, dtype=np.int32)
     rc = _case(lib, b2, rp, ci, 64 * 64 * (n - 1) + 64 * 63)
     assert rc == _lib.VBCSR_OK
+
+
+def _processing_positions(op, fwd):
+    """Processing position of every atom (rank of its panel's start)."""
+    start = np.full(op.n, np.iinfo(np.int64).max)
+    np.minimum.at(start, op.block_rows, fwd)
+    pos = np.empty(op.n, np.int64)
+    pos[np.argsort(start, kind="stable")] = np.arange(op.n)
+    return pos
+
+
+def test_row_order_rcm_and_auto(lib):
+    """RCM is a permutation that shortens the processing distance of coupled
+    atoms of a randomly ordered structure; AUTO takes it there and keeps the
+    lattice order of a lattice."""
+    from workloads.core import random_cube
+    op = random_cube(3000, 0.05, [(1, 600), (4, 1200), (9, 1200)], r_cut=5.0, decay=2.0, seed=7)
+    dist = {}
+    for order in ("atom", "rcm", "auto"):
+        fwd = np.zeros(op.nnzb, np.int64)
+        tr = np.zeros(op.nnzb, np.int64)
+        rc, _, _, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd, tr, order=order)
+        assert rc == 0
+        pos = _processing_positions(op, fwd)
+        assert np.array_equal(np.sort(pos), np.arange(op.n))
+        dist[order] = np.abs(pos[op.block_rows] - pos[op.col_idx]).mean()
+        # blocks of one row stay contiguous and ordered by (b_j, j) in any order
+        key = np.lexsort((op.col_idx, op.b[op.col_idx], pos[op.block_rows]))
+        assert np.all(np.diff(fwd[key]) > 0)
+    assert dist["rcm"] <= 0.5 * dist["atom"]
+    assert dist["auto"] == dist["rcm"]
+    lat = sc_lattice(6, 5, seed=1)
+    fwd = np.zeros(lat.nnzb, np.int64)
+    rc, *_ = _plan(lib, lat.b, lat.row_ptr, lat.col_idx, lat.nnz, fwd, order="auto")
+    assert rc == 0
+    assert np.array_equal(_processing_positions(lat, fwd), np.arange(lat.n))
+
+
+def test_row_order_rejects_unknown(lib):
+    op = random_pattern(3, 10, bset=(2, 3), density=0.3)
+    ns = ctypes.c_int32()
+    shapes = np.zeros(3 * 16, np.int32)
+    pv = ctypes.c_int64()
+    rc = lib.vbcsr_plan_host(op.n, op.b.ctypes.data, op.row_ptr.ctypes.data, op.col_idx.ctypes.data,
+                             op.nnz, ctypes.byref(ns), shapes.ctypes.data, 16, None, None,
+                             ctypes.byref(pv), ctypes.byref(_lib.PlanOpts(0, 0, 0, 7)))
+    assert rc == _lib.VBCSR_EINVAL
 
 
 def test_empty_graph_is_valid(lib):

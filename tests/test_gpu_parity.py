@@ -179,6 +179,37 @@ def test_nonfinite_values_stay_in_their_rows(prec, path, nrhs):
     A.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_row_order_does_not_change_results(prec):
+    """Processing the panels in RCM order instead of atom order leaves every
+    product bit for bit the same (one wave still sums each output row in the
+    same panel order) and matches the oracle; moments agree to rounding."""
+    op = random_pattern(5, 60, bset=(1, 4, 9, 13), density=0.12, empty_rows=3, unsorted=True)
+    rng = np.random.default_rng(12)
+    A1 = Matrix.from_operator(op, prec=prec, row_order="atom")
+    A2 = Matrix.from_operator(op, prec=prec, row_order="rcm")
+    for nrhs in (1, 2, 8, 32, 64):
+        print("case order", prec, nrhs, flush=True)
+        X = dev(rng.standard_normal((op.N, nrhs)), prec)
+        for transpose in (False, True):
+            y1 = host(A1.spmm(X, transpose=transpose))
+            y2 = host(A2.spmm(X, transpose=transpose))
+            assert np.array_equal(y1, y2)
+        if prec != "bf16x3":
+            G = dev(rng.standard_normal((op.N, nrhs)), prec)
+            assert np.array_equal(host(A1.sddmm(G, X)), host(A2.sddmm(G, X)))
+    ref = oracle.spmm(op, rounded(host(X), prec))
+    check(host(A2.spmm(X)), ref, prec)
+    from workloads.core import inf_norm_scale, scaled
+    ops = scaled(op, inf_norm_scale(op))
+    R = rng.standard_normal((op.N, 5))
+    B1 = Matrix.from_operator(ops, prec=prec, row_order="atom")
+    B2 = Matrix.from_operator(ops, prec=prec, row_order="rcm")
+    m1 = B1.cheb_moments(dev(R, prec), 16)
+    m2 = B2.cheb_moments(dev(R, prec), 16)
+    assert np.max(np.abs(m1 - m2)) <= 1e-13 * np.max(np.abs(m1[0]))
+
+
 def test_argument_errors_on_device():
     from paper_2609_04397_amd import _lib, VbcsrError
     import ctypes
