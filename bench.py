@@ -333,6 +333,21 @@ def run_sweep(path):
         A.close()
     emit(dict(size, op="fwd+bwd ratio fp32/fp64", prec="fp32", nrhs=32,
               ms=round(fb["fp32"], 5), ratio=round(fb["fp32"] / fb["fp64"], 4)))
+    del op, vec
+    # the whole degree-64 recurrence of the precision form: plain (64 products)
+    # and with moment doubling (32 products + 32 column dot products)
+    op4, vec4 = make_config("C4", nrhs=64)
+    size = {"workload": "C4", "n_atoms": op4.n, "N": op4.N, "nnzb": op4.nnzb, "n_values": op4.nnz}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        A = Matrix.from_operator(op4, prec=prec)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        R = torch.from_numpy(vec4["R"]).to(dev, dt)
+        ws = torch.empty(A.cheb_workspace_bytes(64, 64), dtype=torch.uint8, device=dev)
+        t_plain = _time_call(lambda: A.cheb_moments(R, 64, workspace=ws), warm=1, reps=3)
+        t_dbl = _time_call(lambda: A.cheb_moments(R, 64, workspace=ws, doubled=True), warm=1, reps=3)
+        emit(dict(size, op="cheb degree 64", prec=prec, nrhs=64, ms=round(t_plain, 4),
+                  doubled_ms=round(t_dbl, 4), speedup=round(t_plain / t_dbl, 3)))
+        A.close()
     out.close()
 
 

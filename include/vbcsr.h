@@ -184,6 +184,23 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
                        void *stream);
 
 /*
+ * vbcsr_cheb_moments_doubled -- the same moments as vbcsr_cheb_moments from
+ * about half the operator applications, for a symmetric A (A_ji = A_ij^T,
+ * the case of the Hamiltonians of section 5).  From the Chebyshev product
+ * identity 2 T_m T_n = T_{m+n} + T_{|m-n|} and the symmetry of T_k(A):
+ *   mu_2k   = 2 <T_k R, T_k R>     - mu_0
+ *   mu_2k+1 = 2 <T_k R, T_{k+1} R> - mu_1
+ * so only T_1 .. T_ceil(degree/2) are formed.  The inner products are FP64
+ * sums in a fixed order (the second one fused into the product's epilogue,
+ * the first a column dot product); the combination above is done in FP64 on
+ * the host.  For a non-symmetric A the result is not the moment sequence.
+ * Arguments, workspace, synchronisation and errors as vbcsr_cheb_moments.
+ */
+int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
+                               int32_t degree, double *mu_host, void *workspace,
+                               int64_t ws_bytes, void *stream);
+
+/*
  * vbcsr_cheb_step -- one step of the Chebyshev recurrence of section 5 with
  * its moment, for callers that drive the recurrence themselves:
  *   T_next = 2 A T_k - T_prev      (written over T_prev, in place)

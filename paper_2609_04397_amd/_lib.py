@@ -47,6 +47,7 @@ SIGNATURES = {
     "vbcsr_sddmm": (_int, [_p, _p, _i64, _p, _i64, _i32, _p, _p]),
     "vbcsr_cheb_workspace_bytes": (_int, [_p, _i32, _i32, ctypes.POINTER(_i64)]),
     "vbcsr_cheb_moments": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),
+    "vbcsr_cheb_moments_doubled": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),
     "vbcsr_cheb_step": (_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i32, _p, _p, _i64, _p]),
     "vbcsr_info": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                           ctypes.POINTER(_i32)]),

@@ -521,6 +521,91 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
   return VBCSR_OK;
 }
 
+int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
+                               int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
+                               void *stream) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
+  if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
+  if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
+  if (!mu_host) return fail(VBCSR_EINVAL, "mu_host is NULL");
+  if (A->N > 0 && !R) return fail(VBCSR_EINVAL, "R is NULL");
+  int64_t need = 0;
+  int rc = vbcsr_cheb_workspace_bytes(A, nrhs, degree, &need);
+  if (rc) return rc;
+  if (workspace && ws_bytes < need) return fail(VBCSR_EINVAL, "workspace too small");
+  if (A->N == 0) {
+    std::fill(mu_host, mu_host + (size_t)(degree + 1) * nrhs, 0.0);
+    return VBCSR_OK;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  void *ws = workspace;
+  if (!ws && (rc = dev_alloc(&ws, (size_t)need))) return rc;
+  const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
+  char *base = static_cast<char *>(ws);
+  void *Ta = base;
+  void *Tb = base + vec;
+  double *parts = reinterpret_cast<double *>(base + 2 * vec);
+  const int64_t nparts = std::max(product_workgroups(A->n), coldot_chunks(A->N));
+  // raw[n]: <R,R> (n = 0), <T_{k-1},T_k> (n = 2k-1), <T_k,T_k> (n = 2k)
+  double *raw = parts + nparts * nrhs;
+  auto coldot = [&](const void *U, int64_t ldu, const void *V, int64_t ldv, double *out) {
+    int64_t nch = 0;
+    hipError_t e2 = A->prec == VBCSR_FP64
+                        ? launch_coldot_f64(static_cast<const double *>(U), ldu,
+                                            static_cast<const double *>(V), ldv, A->N, nrhs, parts,
+                                            &nch, s)
+                        : launch_coldot_f32(static_cast<const float *>(U), ldu,
+                                            static_cast<const float *>(V), ldv, A->N, nrhs, parts,
+                                            &nch, s);
+    if (e2 == hipSuccess) e2 = launch_reduce_partials(parts, nch, nrhs, out, s);
+    return e2;
+  };
+  hipError_t e = coldot(R, ldr, R, ldr, raw);
+  const int64_t npw = product_workgroups(A->n);
+  // T_k for k = 1 .. ceil(degree / 2), each written over T_{k-2} as in the
+  // plain recurrence; the product's moment epilogue weights T_k by T_{k-1}
+  const int32_t kmax = (degree + 1) / 2;
+  const void *prev = R;  // T_{k-2}
+  int64_t ldprev = ldr;
+  const void *cur = R;   // T_{k-1}
+  int64_t ldcur = ldr;
+  for (int32_t k = 1; k <= kmax && e == hipSuccess && rc == VBCSR_OK; ++k) {
+    void *dst;
+    if (k == 1) {
+      dst = Ta;
+      rc = product(A, 0, R, ldr, Ta, nrhs, Ta, nrhs, nrhs, 1.0, 0.0, R, ldr, parts, s);
+    } else {
+      dst = (k == 2) ? Tb : const_cast<void *>(prev);
+      rc = product(A, 0, cur, ldcur, prev, ldprev, dst, nrhs, nrhs, 2.0, -1.0, cur, ldcur, parts, s);
+    }
+    if (rc) break;
+    e = launch_reduce_partials(parts, npw, nrhs, raw + (size_t)(2 * k - 1) * nrhs, s);
+    if (e == hipSuccess && 2 * k <= degree) e = coldot(dst, nrhs, dst, nrhs, raw + (size_t)(2 * k) * nrhs);
+    prev = cur;
+    ldprev = ldcur;
+    cur = dst;
+    ldcur = nrhs;
+  }
+  std::vector<double> r((size_t)(degree + 1) * nrhs);
+  if (e == hipSuccess && rc == VBCSR_OK)
+    e = hipMemcpyAsync(r.data(), raw, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (!workspace) (void)hipFree(ws);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(e, "cheb_moments_doubled");
+  // mu_0 = <R,R>, mu_1 = <R,T_1>, mu_2k = 2<T_k,T_k> - mu_0, mu_2k+1 = 2<T_k,T_k+1> - mu_1
+  for (int32_t c = 0; c < nrhs; ++c) {
+    const double mu0 = r[c];
+    const double mu1 = degree >= 1 ? r[(size_t)nrhs + c] : 0.0;
+    for (int32_t n = 0; n <= degree; ++n) {
+      const double v = r[(size_t)n * nrhs + c];
+      mu_host[(size_t)n * nrhs + c] = n <= 1 ? v : 2.0 * v - ((n & 1) ? mu1 : mu0);
+    }
+  }
+  return VBCSR_OK;
+}
+
 int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev, int64_t ldp,
                     const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
                     int64_t ws_bytes, void *stream) {

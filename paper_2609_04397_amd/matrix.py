@@ -184,17 +184,18 @@ class Matrix:
                                                      ctypes.byref(b)))
         return b.value
 
-    def cheb_moments(self, R, degree: int, workspace=None):
-        """Chebyshev moments ``mu[k, c] = <R_c, T_k(A) R_c>`` (FP64, host array)."""
+    def cheb_moments(self, R, degree: int, workspace=None, doubled: bool = False):
+        """Chebyshev moments ``mu[k, c] = <R_c, T_k(A) R_c>`` (FP64, host array).
+        ``doubled`` uses half the products (symmetric A only)."""
         R = self._vec(R, "R")
         nrhs = R.shape[1]
         mu = np.empty((degree + 1, nrhs), dtype=np.float64)
         ws_ptr, ws_bytes = None, 0
         if workspace is not None:
             ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-        check(_lib.load().vbcsr_cheb_moments(self._h, _ptr(R), R.stride(0) if self.N else nrhs,
-                                             nrhs, int(degree), mu.ctypes.data, ws_ptr, ws_bytes,
-                                             _stream()))
+        fn = _lib.load().vbcsr_cheb_moments_doubled if doubled else _lib.load().vbcsr_cheb_moments
+        check(fn(self._h, _ptr(R), R.stride(0) if self.N else nrhs, nrhs, int(degree),
+                 mu.ctypes.data, ws_ptr, ws_bytes, _stream()))
         return mu
 
 

@@ -33,6 +33,25 @@ def test_cheb_moments_small(prec, nrhs):
     assert np.array_equal(mu, A.cheb_moments(dev(R, prec), deg))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("degree", [0, 1, 2, 3, 63, 64])
+def test_cheb_moments_doubled(prec, degree):
+    """Moments from T_1 .. T_ceil(degree/2) and the Chebyshev product identity
+    equal the plain recurrence's (symmetric operator)."""
+    op, vec = make_config("C4", scale=0.004, nrhs=7)
+    R = vec["R"]
+    print("case doubled", prec, degree, op.N, flush=True)
+    ref = oracle.cheb_moments(op, rounded(R, prec), degree)
+    A = Matrix.from_operator(op, prec=prec)
+    mu = A.cheb_moments(dev(R, prec), degree, doubled=True)
+    err = np.max(np.abs(mu - ref)) / np.max(np.abs(ref[0]))
+    print("doubled moment error", prec, degree, err)
+    # the FP32/BF16x3 vectors enter twice in <T_k, T_k>: twice the bound
+    assert err <= (1 if prec == "fp64" else 2) * MOM_TOL[prec]
+    ws = torch.empty(A.cheb_workspace_bytes(7, degree), dtype=torch.uint8, device="cuda")
+    assert np.array_equal(mu, A.cheb_moments(dev(R, prec), degree, workspace=ws, doubled=True))
+
+
 def test_cheb_moments_mixed_blocks_and_workspace():
     op = random_pattern(14, 60, bset=(1, 4, 9, 13, 20), density=0.1, symmetric=True, empty_rows=2)
     from workloads.core import inf_norm_scale, scaled

@@ -144,6 +144,21 @@ def test_c4_moments_full_size_low_degree(c2):
         A.close()
 
 
+@pytest.mark.timeout(400)
+def test_c4_doubled_moments_full_size():
+    """Degree 6 from 3 products at the full C4 size, every precision form."""
+    op4, vec = make_config("C4", nrhs=64)
+    R = vec["R"]
+    ref = oracle.cheb_moments(op4, R, 6)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 1e-4)):
+        A = Matrix.from_operator(op4, prec=prec)
+        mu = A.cheb_moments(dev(R, prec), 6, doubled=True)
+        err = np.max(np.abs(mu - ref)) / np.max(np.abs(ref[0]))
+        print("C4 doubled moments %s degree 6 err %.3e" % (prec, err))
+        assert err <= tol
+        A.close()
+
+
 @pytest.mark.timeout(300)
 def test_c5_fwd_bwd_fp32_sampled():
     op, vec = make_config("C5")
