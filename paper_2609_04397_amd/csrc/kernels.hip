@@ -897,11 +897,15 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
         // the FP64/FP32 kernel: indices run two steps ahead, values and X
         // rows one step ahead.
         auto ld_idx = [&](int s, int32_t(&xi)[8]) {
+          // the 8 column indices of the lane's group: two 16-byte loads
+          // (past the panel's table the buffer reads zero; masked by k < K)
+          const int k0 = (s * 4 + kg) * 8;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const int k = (s * 4 + kg) * 8 + u;
-            const int32_t v = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)k * 4, 0, 0);
-            xi[u] = k < K ? v : -1;
+          for (int h = 0; h < 2; ++h) {
+            const v4u32 q = __builtin_bit_cast(
+                v4u32, __builtin_amdgcn_raw_buffer_load_b128(rc, (uint32_t)(k0 + 4 * h) * 4, 0, 0));
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xi[4 * h + u] = k0 + 4 * h + u < K ? (int32_t)q[u] : -1;
           }
         };
         auto ld_val = [&](int s, v8u &h, v8u &l) {
