@@ -286,6 +286,33 @@ def run_sweep(path):
                 "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "roofline_frac": round(roof / ms, 4), "alg_bytes": int(nbytes)}
 
+    # C1 (17.5 MB) stays in the 256 MB MALL between calls: also time it cold
+    # (a 1 GiB scratch write before every call) and as a 1000-launch average
+    op1, _ = make_config("C1", nrhs=1)
+    A1 = Matrix.from_operator(op1)
+    X1c = torch.randn((op1.N, 16), dtype=torch.float64, device=dev)
+    Y1c = torch.empty_like(X1c)
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    cold = []
+    for _ in range(7):
+        scratch.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        A1.spmm(X1c, Y1c)
+        e1.record()
+        e1.synchronize()
+        cold.append(e0.elapsed_time(e1))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(1000):
+        A1.spmm(X1c, Y1c)
+    e1.record()
+    e1.synchronize()
+    size1 = {"workload": "C1", "n_atoms": op1.n, "N": op1.N, "nnzb": op1.nnzb, "n_values": op1.nnz}
+    emit(dict(size1, op="spmm cold", prec="fp64", nrhs=16, **rate(op1, "fp64", 16, float(np.median(cold)))))
+    emit(dict(size1, op="spmm 1000-launch mean", prec="fp64", nrhs=16,
+              **rate(op1, "fp64", 16, e0.elapsed_time(e1) / 1000)))
+    del scratch, A1, X1c, Y1c
     plan = [("C1", [("fp64", (1, 2, 4, 8, 16), True)]),
             ("C2", [("fp64", (1, 2, 4, 8, 16, 32, 64), True), ("fp32", (1, 8, 64), False),
                     ("bf16x3", (64,), False)]),
@@ -394,13 +421,40 @@ def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, budget_s=12.0):
             break
     med = {k: float(np.median(v)) for k, v in per.items()}
     step_s = sum(med.values())
+    cores = oracle.max_threads()
+    # the same oracle on one thread (bitwise the same results), on the SpMV
+    # and the nrhs-32 SpMM only: the whole step would take ~20 s there
+    oracle.set_threads(1)
+    try:
+        t1 = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.csr_spmm(A, X1)
+            oracle.csr_spmm(A, X32)
+            t1.append(time.perf_counter() - t0)
+    finally:
+        oracle.set_threads(cores)
+    one = float(np.median(t1))
+    one_bytes = algorithmic_bytes(op, 1, 8, 8, "product") + algorithmic_bytes(op, 32, 8, 8, "product")
+    cpu_model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": round(step_bytes / step_s / 1e9, 3), "unit": "GB/s",
-            "cores": oracle.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": "the whole step (7 products, full size) on the FP64 scalar-CSR oracle, "
                       "median of %d repetitions (%.1f s of CPU work); expansion/transpose "
                       "excluded; FP32/BF16x3 forms run as FP64" % (reps, time.perf_counter() - t_all),
             "step_s": round(step_s, 4),
-            "per_kernel_s": {k: round(v, 4) for k, v in med.items()}}
+            "per_kernel_s": {k: round(v, 4) for k, v in med.items()},
+            "single_thread": {"value": round(one_bytes / one / 1e9, 3), "unit": "GB/s",
+                              "sample": "spmv_fp64 + spmm_fp64 (nrhs 32), median of 3",
+                              "s": round(one, 4)},
+            "cpu_model": cpu_model, "host_threads": os.cpu_count()}
 
 
 def traffic_record(kernel):
