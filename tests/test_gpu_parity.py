@@ -33,7 +33,8 @@ def pattern(request):
 
 
 @pytest.mark.parametrize("path,nrhs", [("vec", 1), ("vec", 2), ("vec", 3), ("vec", 8), ("vec", 11),
-                                       ("mfma", 1), ("mfma", 16), ("mfma", 33), ("mfma", 64)])
+                                       ("mfma", 1), ("mfma", 16), ("mfma", 33), ("mfma", 64),
+                                       ("mfma", 100), ("mfma", 128)])
 def test_fp64_forward_and_transpose(pattern, path, nrhs):
     name, op = pattern
     print("case", name, path, nrhs, flush=True)
@@ -50,7 +51,7 @@ def test_fp64_forward_and_transpose(pattern, path, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("nrhs", [1, 8, 16, 40])
+@pytest.mark.parametrize("nrhs", [1, 8, 16, 40, 100, 128])
 def test_reduced_precision_forward(pattern, prec, nrhs):
     name, op = pattern
     print("case", name, prec, nrhs, flush=True)
@@ -64,7 +65,7 @@ def test_reduced_precision_forward(pattern, prec, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("nrhs", [1, 7, 32])
+@pytest.mark.parametrize("nrhs", [1, 7, 32, 64, 100])
 def test_sddmm(pattern, prec, nrhs):
     name, op = pattern
     print("case sddmm", name, prec, nrhs, flush=True)
