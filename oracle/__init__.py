@@ -14,7 +14,10 @@ Every function follows one definition from the paper:
 * :func:`sddmm`       block-sampled ``dA_ij = dY_i X_j^T`` (the gradient of
   ``sum(Y * G)`` with respect to the stored blocks);
 * :func:`cheb_moments` Chebyshev moments ``mu_k = <R, T_k(A) R>`` of the
-  kernel polynomial method (section 5), FP64 throughout.
+  kernel polynomial method (section 5), FP64 throughout;
+* :func:`spgemm`      thresholded block product ``C_ij = sum_k A_ik B_kj``
+  (section 3.2, equation 2): symbolic stage with the block-norm bound of
+  equation 3, numeric stage, final block-norm filter.
 """
 from __future__ import annotations
 
@@ -68,6 +71,16 @@ def _load():
     lib.oracle_cheb.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p, ctypes.c_int64,
                                 ctypes.c_int32, ctypes.c_int32, _f64p]
     lib.oracle_cheb.restype = ctypes.c_int
+    lib.oracle_seq_norms.argtypes = [ctypes.c_int64, _i64p, _f64p, _f64p]
+    lib.oracle_seq_norms.restype = None
+    lib.oracle_spgemm_symbolic.argtypes = [ctypes.c_int32, _i64p, _i32p, _f64p, _i64p, _i32p,
+                                           _f64p, ctypes.c_double, _i64p, ctypes.c_int64, _i64p,
+                                           _i32p, _f64p, ctypes.c_int64]
+    lib.oracle_spgemm_symbolic.restype = ctypes.c_int64
+    lib.oracle_spgemm_numeric.argtypes = [ctypes.c_int32, _i32p, _i64p, _i32p, _f64p, _i64p,
+                                          _i32p, _f64p, _i64p, ctypes.c_int64, _i64p, _i32p,
+                                          _f64p]
+    lib.oracle_spgemm_numeric.restype = None
     lib.oracle_max_threads.restype = ctypes.c_int
     lib.oracle_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -202,3 +215,78 @@ def abs_product(op, X, values=None, transpose_op=False) -> np.ndarray:
     if transpose_op:
         A = transpose(A)
     return csr_spmm(A, np.abs(X))
+
+
+def seq_norms(sizes, values) -> np.ndarray:
+    """Frobenius norms of blocks stored back to back (``sizes[t]`` values each)."""
+    sizes = _c(sizes, np.int64)
+    out = np.empty(max(sizes.shape[0], 1))
+    _load().oracle_seq_norms(sizes.shape[0], sizes, _c(values, np.float64) if values.size
+                             else np.zeros(1), out)
+    return out[:sizes.shape[0]]
+
+
+def block_norms(op, values=None) -> np.ndarray:
+    """Frobenius norm of every stored block of ``op``, graph order."""
+    r = np.repeat(np.arange(op.b.shape[0]), np.diff(op.row_ptr))
+    sizes = op.b[r].astype(np.int64) * op.b[op.col_idx].astype(np.int64)
+    return seq_norms(sizes, op.values if values is None else values)
+
+
+def spgemm(A, B, eps: float = 0.0, rows=None) -> dict:
+    """Thresholded block product ``C = A B`` (section 3.2, equations 2 and 3).
+
+    ``A`` and ``B`` are operators over the same atoms.  For the block rows
+    ``rows`` (all by default) returns a dict with
+
+    * ``sym_rp``, ``sym_col``, ``bound``: the symbolic pattern, i.e. the
+      candidates (i, j) with ``U_ij = sum_k ||A_ik|| ||B_kj|| >= eps``
+      (row-pointer over ``rows``, ascending columns, the bound of each);
+    * ``sym_values``: the numeric blocks of that pattern, row-major, back to
+      back in pattern order;
+    * ``rp``, ``col``, ``values``, ``norms``: the result after the final
+      filter, which keeps the blocks whose Frobenius norm is at least ``eps``.
+    """
+    if not np.array_equal(np.asarray(A.b), np.asarray(B.b)):
+        raise ValueError("A and B must share the atoms (block sizes)")
+    b = _c(A.b, np.int32)
+    n = b.shape[0]
+    rows = np.arange(n, dtype=np.int64) if rows is None else _c(rows, np.int64)
+    arp, aci = _c(A.row_ptr, np.int64), _c(A.col_idx, np.int32)
+    brp, bci = _c(B.row_ptr, np.int64), _c(B.col_idx, np.int32)
+    an, bn = block_norms(A), block_norms(B)
+    blen = np.diff(brp)
+    cap = 1
+    for i in rows:
+        cap += int(blen[aci[arp[i]:arp[i + 1]]].sum())
+    cnt = np.zeros(max(rows.shape[0], 1), dtype=np.int64)
+    col = np.empty(cap, dtype=np.int32)
+    bound = np.empty(cap)
+    tot = _load().oracle_spgemm_symbolic(n, arp, aci, an if an.size else np.zeros(1), brp, bci,
+                                         bn if bn.size else np.zeros(1), float(eps), rows,
+                                         rows.shape[0], cnt, col, bound, cap)
+    if tot < 0:
+        raise RuntimeError("oracle_spgemm_symbolic: capacity exceeded")
+    sym_rp = np.zeros(rows.shape[0] + 1, dtype=np.int64)
+    np.cumsum(cnt[:rows.shape[0]], out=sym_rp[1:])
+    sym_col = col[:tot].copy()
+    bound = bound[:tot].copy()
+    rowb = np.repeat(b[rows].astype(np.int64), np.diff(sym_rp))
+    sizes = rowb * b[sym_col].astype(np.int64)
+    vals = np.empty(max(int(sizes.sum()), 1))
+    _load().oracle_spgemm_numeric(n, b, arp, aci, _c(A.values, np.float64), brp, bci,
+                                  _c(B.values, np.float64), rows, rows.shape[0], sym_rp,
+                                  sym_col if tot else np.zeros(1, np.int32), vals)
+    vals = vals[:int(sizes.sum())]
+    norms = seq_norms(sizes, vals)
+    keep = ~(norms < eps)
+    base = np.zeros(tot + 1, dtype=np.int64)
+    np.cumsum(sizes, out=base[1:])
+    kept_vals = np.concatenate([vals[base[t]:base[t + 1]] for t in np.nonzero(keep)[0]]) \
+        if keep.any() else np.zeros(0)
+    t_row = np.repeat(np.arange(rows.shape[0]), np.diff(sym_rp))
+    rp = np.zeros(rows.shape[0] + 1, dtype=np.int64)
+    np.cumsum(np.bincount(t_row[keep], minlength=rows.shape[0]), out=rp[1:])
+    return {"rows": rows, "sym_rp": sym_rp, "sym_col": sym_col, "bound": bound,
+            "sym_values": vals, "rp": rp, "col": sym_col[keep].copy(), "values": kept_vals,
+            "norms": norms[keep].copy()}

@@ -211,3 +211,124 @@ int oracle_cheb(int64_t N, const int64_t *rp, const int32_t *ci, const double *v
   free(t_cur);
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Thresholded block product C = A B (section 3.2, equations 2 and 3).
+ * A and B are square operators over the same atoms (same b).
+ * ---------------------------------------------------------------------- */
+
+/* Frobenius norms of nblk blocks stored one after the other (block t has
+ * size[t] values): the square root of the sum of the squares of its values,
+ * summed in storage (row-major) order. */
+void oracle_seq_norms(int64_t nblk, const int64_t *size, const double *vals, double *norms) {
+  int64_t base = 0;
+  for (int64_t t = 0; t < nblk; ++t) {
+    double s = 0.0;
+    for (int64_t e = 0; e < size[t]; ++e) s += vals[base + e] * vals[base + e];
+    norms[t] = sqrt(s);
+    base += size[t];
+  }
+}
+
+/* Symbolic stage for the block rows rows[0..nrows).  For row i the candidate
+ * columns are the columns j of every row k of B with a stored block (i, k)
+ * in A; each candidate carries the bound of equation 3,
+ *   U_ij = sum_k ||A_ik|| ||B_kj||,
+ * summed over k in the order row i of A stores its blocks.  A candidate is
+ * rejected when U_ij < eps.  The kept columns of each row are written in
+ * ascending order to col[], their bounds to bound[], and cnt[t] receives
+ * the number kept in row rows[t].  Returns the total, or -1 when it would
+ * exceed cap.                                                              */
+int64_t oracle_spgemm_symbolic(int32_t n, const int64_t *arp, const int32_t *aci,
+                               const double *an, const int64_t *brp, const int32_t *bci,
+                               const double *bn, double eps, const int64_t *rows,
+                               int64_t nrows, int64_t *cnt, int32_t *col, double *bound,
+                               int64_t cap) {
+  double *acc = (double *)calloc((size_t)n + 1, sizeof(double));
+  char *seen = (char *)calloc((size_t)n + 1, 1);
+  int64_t total = 0;
+  for (int64_t t = 0; t < nrows; ++t) {
+    int64_t i = rows[t];
+    for (int64_t ka = arp[i]; ka < arp[i + 1]; ++ka) {
+      int32_t k = aci[ka];
+      for (int64_t kb = brp[k]; kb < brp[k + 1]; ++kb) {
+        int32_t j = bci[kb];
+        seen[j] = 1;
+        acc[j] += an[ka] * bn[kb];
+      }
+    }
+    /* ascending scan of the atom range keeps the columns sorted */
+    int64_t kept = 0;
+    for (int32_t j = 0; j < n; ++j) {
+      if (!seen[j]) continue;
+      if (!(acc[j] < eps)) {
+        if (total + kept >= cap) { free(acc); free(seen); return -1; }
+        col[total + kept] = j;
+        bound[total + kept] = acc[j];
+        ++kept;
+      }
+      seen[j] = 0;
+      acc[j] = 0.0;
+    }
+    cnt[t] = kept;
+    total += kept;
+  }
+  free(acc);
+  free(seen);
+  return total;
+}
+
+/* Numeric stage: the blocks C_ij = sum_k A_ik B_kj (equation 2) of a given
+ * pattern, for the block rows rows[0..nrows) whose kept columns are
+ * col[crp[t] .. crp[t+1]) (ascending).  Element (p, q) of C_ij is one
+ * sequential FP64 sum over k in the order row i of A stores its blocks, then
+ * over the inner index ascending.  Blocks are written row-major, one after
+ * the other in pattern order, to out[].                                     */
+void oracle_spgemm_numeric(int32_t n, const int32_t *b, const int64_t *arp, const int32_t *aci,
+                           const double *av, const int64_t *brp, const int32_t *bci,
+                           const double *bv, const int64_t *rows, int64_t nrows,
+                           const int64_t *crp, const int32_t *col, double *out) {
+  int64_t *abase = (int64_t *)malloc(sizeof(int64_t) * ((size_t)arp[n] + 1));
+  int64_t *bbase = (int64_t *)malloc(sizeof(int64_t) * ((size_t)brp[n] + 1));
+  int64_t *slot = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1));
+  abase[0] = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t k = arp[i]; k < arp[i + 1]; ++k)
+      abase[k + 1] = abase[k] + (int64_t)b[i] * b[aci[k]];
+  bbase[0] = 0;
+  for (int32_t i = 0; i < n; ++i)
+    for (int64_t k = brp[i]; k < brp[i + 1]; ++k)
+      bbase[k + 1] = bbase[k] + (int64_t)b[i] * b[bci[k]];
+  for (int32_t j = 0; j < n; ++j) slot[j] = -1;
+  int64_t obase = 0;
+  for (int64_t t = 0; t < nrows; ++t) {
+    int64_t i = rows[t];
+    int32_t bi = b[i];
+    /* output position of every kept column of this row */
+    for (int64_t c = crp[t]; c < crp[t + 1]; ++c) {
+      slot[col[c]] = obase;
+      int64_t sz = (int64_t)bi * b[col[c]];
+      for (int64_t e = 0; e < sz; ++e) out[obase + e] = 0.0;
+      obase += sz;
+    }
+    for (int64_t ka = arp[i]; ka < arp[i + 1]; ++ka) {
+      int32_t k = aci[ka];
+      int32_t bk = b[k];
+      const double *A = av + abase[ka];
+      for (int64_t kb = brp[k]; kb < brp[k + 1]; ++kb) {
+        int32_t j = bci[kb];
+        if (slot[j] < 0) continue;
+        int32_t bj = b[j];
+        const double *B = bv + bbase[kb];
+        double *C = out + slot[j];
+        for (int32_t p = 0; p < bi; ++p)
+          for (int32_t q = 0; q < bj; ++q)
+            for (int32_t s = 0; s < bk; ++s) C[p * bj + q] += A[p * bk + s] * B[s * bj + q];
+      }
+    }
+    for (int64_t c = crp[t]; c < crp[t + 1]; ++c) slot[col[c]] = -1;
+  }
+  free(slot);
+  free(bbase);
+  free(abase);
+}
