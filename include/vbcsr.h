@@ -22,8 +22,8 @@
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
  * are enqueued asynchronously; the library synchronises the device only in
- * vbcsr_create, vbcsr_set_values (host input), vbcsr_cheb_moments and
- * vbcsr_destroy.  A handle is immutable except through vbcsr_set_values;
+ * vbcsr_create, vbcsr_set_values (host input), vbcsr_cheb_moments(_doubled),
+ * vbcsr_spgemm, vbcsr_get_structure and vbcsr_destroy.  A handle is immutable except through vbcsr_set_values;
  * products on different streams may run concurrently on one handle, but
  * must not overlap a vbcsr_set_values on it.
  */
@@ -242,6 +242,65 @@ int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *
                     const int32_t *col_idx, int64_t n_values, int32_t *n_shapes,
                     int32_t *shapes, int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos,
                     int64_t *page_values, const vbcsr_plan_opts *opts);
+
+/*
+ * vbcsr_get_structure -- copy the block graph of a handle to the host.
+ *   block_sizes  out [n_atoms]; row_ptr out [n_atoms+1]; col_idx out [nnzb]
+ *   (sizes from vbcsr_info; n_atoms = number of block rows).  Synchronous.
+ * Errors: EINVAL (null handle or output), EHIP.
+ */
+int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_ptr,
+                        int32_t *col_idx);
+
+/*
+ * vbcsr_get_values -- the handle's block values in graph order, each block
+ * row-major (the layout vbcsr_create takes), written by a kernel on `stream`.
+ *   values  device, n_values elements of the handle's type
+ *   dtype   0 = double (FP64 handles), 1 = float (FP32 handles)
+ * Errors: EINVAL, EUNSUPPORTED (BF16X3 handles keep only the split pages), EHIP.
+ */
+int vbcsr_get_values(const vbcsr_mat *A, void *values, int dtype, void *stream);
+
+/* Counts and phase times of one vbcsr_spgemm call. */
+typedef struct {
+  int64_t candidates;    /* distinct (i, j) reached through some k               */
+  int64_t kept_symbolic; /* candidates whose bound is not below eps              */
+  int64_t nnzb;          /* blocks of C after the final filter                   */
+  int64_t products;      /* block products A_ik B_kj evaluated                   */
+  double flops;          /* sum over evaluated products of 2 b_i b_k b_j         */
+  double ms_norms;       /* structure copy-back and block norms of A and B      */
+  double ms_symbolic;    /* host symbolic stage and upload of its lists         */
+  double ms_numeric;     /* numeric kernel (device events around it)            */
+  double ms_filter;      /* final filter: norms back and compaction             */
+  double ms_build;       /* planning and packing of C                           */
+} vbcsr_spgemm_stats;
+
+/*
+ * vbcsr_spgemm -- thresholded block product C = A B.
+ * Paper: section 3.2, equation 2 (C_ij = sum_k A_ik B_kj) and equation 3
+ * (||C_ij|| <= sum_k ||A_ik|| ||B_kj||).  Stages:
+ *   1. block norms of A and B (Frobenius, on the device; only when eps > 0);
+ *   2. symbolic stage on the host: the candidates of row i are the columns j
+ *      of the rows k of B with a block (i, k) in A; a candidate is rejected
+ *      when U_ij = sum_k ||A_ik|| ||B_kj|| (summed over k in A's stored order)
+ *      is below eps.  Kept columns are ascending in every row of C;
+ *   3. numeric stage on the device, one wave per output block: the products
+ *      A_ik B_kj of the block in A's stored order of k, on matrix cores, FP64;
+ *   4. final filter: computed blocks whose Frobenius norm is below eps are
+ *      removed (nothing is removed at eps = 0);
+ *   5. C is planned and packed like a vbcsr_create result.
+ *   out     receives the new FP64 handle C over the same atoms (NULL on failure)
+ *   A, B    FP64 handles over the same atoms (same block sizes)
+ *   eps     block-norm threshold, >= 0
+ *   opts    planner options of C (may be NULL)
+ *   stats   may be NULL
+ * Synchronises `stream` (the symbolic stage needs the norms on the host).
+ * Errors: EINVAL (null arguments, different atoms, eps < 0 or NaN, bad
+ * options), EUNSUPPORTED (non-FP64 handles, or C outside vbcsr_create's
+ * limits), ENOMEM, EHIP.
+ */
+int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double eps,
+                 const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream);
 
 /* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
 void vbcsr_destroy(vbcsr_mat *A);

@@ -38,6 +38,14 @@ class PlanOpts(ctypes.Structure):
                 ("path", ctypes.c_int32), ("row_order", ctypes.c_int32)]
 
 
+class SpgemmStats(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("kept_symbolic", ctypes.c_int64),
+                ("nnzb", ctypes.c_int64), ("products", ctypes.c_int64),
+                ("flops", ctypes.c_double), ("ms_norms", ctypes.c_double),
+                ("ms_symbolic", ctypes.c_double), ("ms_numeric", ctypes.c_double),
+                ("ms_filter", ctypes.c_double), ("ms_build", ctypes.c_double)]
+
+
 SIGNATURES = {
     "vbcsr_create": (_int, [ctypes.POINTER(_p), _i32, _p, _p, _p, _p, _i64, _int,
                             ctypes.POINTER(PlanOpts), _p]),
@@ -53,6 +61,10 @@ SIGNATURES = {
                           ctypes.POINTER(_i32)]),
     "vbcsr_plan_host": (_int, [_i32, _p, _p, _p, _i64, ctypes.POINTER(_i32), _p, _i32, _p, _p,
                                ctypes.POINTER(_i64), ctypes.POINTER(PlanOpts)]),
+    "vbcsr_get_structure": (_int, [_p, _p, _p, _p]),
+    "vbcsr_get_values": (_int, [_p, _p, _int, _p]),
+    "vbcsr_spgemm": (_int, [ctypes.POINTER(_p), _p, _p, _f64, ctypes.POINTER(PlanOpts),
+                            ctypes.POINTER(SpgemmStats), _p]),
     "vbcsr_destroy": (None, [_p]),
     "vbcsr_last_error": (ctypes.c_char_p, []),
 }

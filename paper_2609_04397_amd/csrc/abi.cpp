@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -261,32 +262,12 @@ int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int3
   return VBCSR_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *vbcsr_last_error(void) { return g_last_error.c_str(); }
-
-int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
-                    const int32_t *col_idx, int64_t n_values, int32_t *n_shapes, int32_t *shapes,
-                    int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values,
-                    const vbcsr_plan_opts *opts) {
-  HostPlan plan;
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
-  if (rc) return rc;
-  if (n_shapes) *n_shapes = (int32_t)plan.shapes.size();
-  if (shapes)
-    for (int32_t t = 0; t < std::min<int32_t>(max_shapes, (int32_t)plan.shapes.size()); ++t)
-      for (int c = 0; c < 3; ++c) shapes[3 * t + c] = plan.shapes[t][c];
-  if (fwd_pos) std::copy(plan.fwd.blk_pos.begin(), plan.fwd.blk_pos.end(), fwd_pos);
-  if (tr_pos) std::copy(plan.tr.blk_pos.begin(), plan.tr.blk_pos.end(), tr_pos);
-  if (page_values) *page_values = plan.fwd.n_values;
-  return VBCSR_OK;
-}
-
-int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
-                 const int64_t *row_ptr, const int32_t *col_idx, const double *values,
-                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream) {
+// Shared by vbcsr_create (host values) and the block product (device values
+// in graph order).
+int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
+                const int64_t *row_ptr, const int32_t *col_idx, const void *values,
+                bool values_on_device, int64_t n_values, vbcsr_prec prec,
+                const vbcsr_plan_opts *opts, void *stream) {
   if (!out) return fail(VBCSR_EINVAL, "out is NULL");
   *out = nullptr;
   if (prec != VBCSR_FP64 && prec != VBCSR_FP32 && prec != VBCSR_BF16X3)
@@ -357,7 +338,12 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     }
   }
   // initial values: host graph order -> device staging -> pages
-  if (plan.nnz > 0) {
+  if (plan.nnz > 0 && values_on_device) {
+    rc = pack_all(A, values, 0, s);
+    hipError_t e = hipStreamSynchronize(s);
+    if (rc) return bail(rc);
+    if (e != hipSuccess) return bail(hip_fail(e, "create"));
+  } else if (plan.nnz > 0) {
     double *stage = nullptr;
     if ((rc = dev_alloc(reinterpret_cast<void **>(&stage), sizeof(double) * plan.nnz))) return bail(rc);
     hipError_t e = values ? hipMemcpyAsync(stage, values, sizeof(double) * plan.nnz,
@@ -376,6 +362,71 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   }
   *out = A;
   return VBCSR_OK;
+}
+
+
+// Device allocations that live for one call; freed (after the stream has
+// been synchronised by the caller) when the object goes out of scope.
+struct TempAllocs {
+  std::vector<void *> ptrs;
+  template <typename T>
+  int alloc(T **p, size_t count) {
+    int rc = dev_alloc(reinterpret_cast<void **>(p), sizeof(T) * count);
+    if (rc == VBCSR_OK && *p) ptrs.push_back(*p);
+    return rc;
+  }
+  template <typename T>
+  int up(T **p, const std::vector<T> &v, hipStream_t s) {
+    int rc = upload(p, v, s);
+    if (rc == VBCSR_OK && *p) ptrs.push_back(*p);
+    return rc;
+  }
+  ~TempAllocs() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+int d2h(std::vector<T> &dst, const T *src, size_t count, hipStream_t s) {
+  dst.resize(count);
+  if (count == 0) return VBCSR_OK;
+  HIP_TRY(hipMemcpyAsync(dst.data(), src, sizeof(T) * count, hipMemcpyDeviceToHost, s),
+          "hipMemcpyAsync");
+  return VBCSR_OK;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vbcsr_last_error(void) { return g_last_error.c_str(); }
+
+int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
+                    const int32_t *col_idx, int64_t n_values, int32_t *n_shapes, int32_t *shapes,
+                    int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values,
+                    const vbcsr_plan_opts *opts) {
+  HostPlan plan;
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
+  if (rc) return rc;
+  if (n_shapes) *n_shapes = (int32_t)plan.shapes.size();
+  if (shapes)
+    for (int32_t t = 0; t < std::min<int32_t>(max_shapes, (int32_t)plan.shapes.size()); ++t)
+      for (int c = 0; c < 3; ++c) shapes[3 * t + c] = plan.shapes[t][c];
+  if (fwd_pos) std::copy(plan.fwd.blk_pos.begin(), plan.fwd.blk_pos.end(), fwd_pos);
+  if (tr_pos) std::copy(plan.tr.blk_pos.begin(), plan.tr.blk_pos.end(), tr_pos);
+  if (page_values) *page_values = plan.fwd.n_values;
+  return VBCSR_OK;
+}
+
+int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
+                 const int64_t *row_ptr, const int32_t *col_idx, const double *values,
+                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream) {
+  return create_impl(out, n_atoms, block_sizes, row_ptr, col_idx, values, false, n_values, prec,
+                     opts, stream);
 }
 
 int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream) {
@@ -643,6 +694,198 @@ void vbcsr_destroy(vbcsr_mat *A) {
   if (!A) return;
   free_all(A);
   delete A;
+}
+
+int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_ptr,
+                        int32_t *col_idx) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if ((A->n && (!block_sizes || !row_ptr)) || (A->nnzb && !col_idx))
+    return fail(VBCSR_EINVAL, "output pointer is NULL");
+  if (A->n) {
+    HIP_TRY(hipMemcpy(block_sizes, A->b, sizeof(int32_t) * A->n, hipMemcpyDeviceToHost),
+            "hipMemcpy");
+    HIP_TRY(hipMemcpy(row_ptr, A->row_ptr, sizeof(int64_t) * (A->n + 1), hipMemcpyDeviceToHost),
+            "hipMemcpy");
+  } else if (row_ptr) {
+    row_ptr[0] = 0;
+  }
+  if (A->nnzb)
+    HIP_TRY(hipMemcpy(col_idx, A->col_idx, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToHost),
+            "hipMemcpy");
+  return VBCSR_OK;
+}
+
+int vbcsr_get_values(const vbcsr_mat *A, void *values, int dtype, void *stream) {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (A->prec == VBCSR_BF16X3)
+    return fail(VBCSR_EUNSUPPORTED, "BF16X3 handles keep only the split pages");
+  const int want = A->prec == VBCSR_FP64 ? 0 : 1;
+  if (dtype != want) return fail(VBCSR_EINVAL, "dtype must match the handle (0 FP64, 1 FP32)");
+  if (A->nnz == 0) return VBCSR_OK;
+  if (!values) return fail(VBCSR_EINVAL, "values is NULL");
+  const DevDir &D = A->dir[0];
+  hipError_t e = launch_unpack(D.vals, A->prec == VBCSR_FP64 ? 8 : 4, D.blk_pos, A->blk_row,
+                               A->col_idx, A->b, A->gbase, A->nnzb, values,
+                               static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "unpack kernel launch");
+  return VBCSR_OK;
+}
+
+int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double eps,
+                 const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream) {
+  using clk = std::chrono::steady_clock;
+  if (!out) return fail(VBCSR_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!A || !B) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (!(eps >= 0.0)) return fail(VBCSR_EINVAL, "eps must be >= 0");
+  if (A->prec != VBCSR_FP64 || B->prec != VBCSR_FP64)
+    return fail(VBCSR_EUNSUPPORTED, "the block product takes FP64 handles");
+  if (A->n != B->n) return fail(VBCSR_EINVAL, "A and B must be over the same atoms");
+  if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA ||
+               opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
+    return fail(VBCSR_EINVAL, "invalid plan options");
+  vbcsr_spgemm_stats st{};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n = A->n;
+  TempAllocs tmp;
+  int rc;
+
+  // structure and page positions back to the host
+  auto t0 = clk::now();
+  std::vector<int32_t> b, bb, aci, bci;
+  std::vector<int64_t> arp, brp, apos, bpos;
+  if ((rc = d2h(b, A->b, n, s)) || (rc = d2h(bb, B->b, n, s)) ||
+      (rc = d2h(arp, A->row_ptr, (size_t)n + 1, s)) || (rc = d2h(brp, B->row_ptr, (size_t)n + 1, s)) ||
+      (rc = d2h(aci, A->col_idx, A->nnzb, s)) || (rc = d2h(bci, B->col_idx, B->nnzb, s)) ||
+      (rc = d2h(apos, A->dir[0].blk_pos, A->nnzb, s)) ||
+      (rc = d2h(bpos, B->dir[1].blk_pos, B->nnzb, s)))
+    return rc;
+  // block norms, needed only to compare with a positive threshold
+  std::vector<double> an, bn;
+  if (eps > 0.0) {
+    double *dn = nullptr;
+    if ((rc = tmp.alloc(&dn, (size_t)(A->nnzb + B->nnzb)))) return rc;
+    hipError_t e = launch_block_norms(static_cast<const double *>(A->dir[0].vals),
+                                      A->dir[0].blk_pos, A->blk_row, A->col_idx, A->b, A->nnzb,
+                                      dn, s);
+    if (e == hipSuccess)
+      e = launch_block_norms(static_cast<const double *>(B->dir[0].vals), B->dir[0].blk_pos,
+                             B->blk_row, B->col_idx, B->b, B->nnzb, dn + A->nnzb, s);
+    if (e != hipSuccess) return hip_fail(e, "block norm kernel launch");
+    if ((rc = d2h(an, dn, A->nnzb, s)) || (rc = d2h(bn, dn + A->nnzb, B->nnzb, s))) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(s), "spgemm");
+  if (b != bb) return fail(VBCSR_EINVAL, "A and B must be over the same atoms (block sizes differ)");
+  st.ms_norms = ms_since(t0);
+
+  // symbolic stage (host) and its lists on the device
+  t0 = clk::now();
+  SpgemmPlan plan;
+  spgemm_symbolic(n, b.data(), arp.data(), aci.data(), apos.data(),
+                  eps > 0.0 ? an.data() : nullptr, brp.data(), bci.data(), bpos.data(),
+                  eps > 0.0 ? bn.data() : nullptr, eps, plan);
+  const int64_t nC = (int64_t)plan.oi.size();
+  const int64_t nvals = plan.obase[nC];
+  st.candidates = plan.candidates;
+  st.kept_symbolic = nC;
+  st.products = (int64_t)plan.pa.size();
+  st.flops = plan.flops;
+  SpgemmParams sp{};
+  sp.avals = static_cast<const double *>(A->dir[0].vals);
+  sp.bvals = static_cast<const double *>(B->dir[1].vals);
+  sp.b = A->b;
+  sp.nC = nC;
+  int32_t *d_oi = nullptr, *d_oj = nullptr;
+  int64_t *d_obase = nullptr, *d_pptr = nullptr, *d_pa = nullptr, *d_pb = nullptr;
+  double *cvals = nullptr, *cnorm = nullptr;
+  if ((rc = tmp.up(&d_oi, plan.oi, s)) || (rc = tmp.up(&d_oj, plan.oj, s)) ||
+      (rc = tmp.up(&d_obase, plan.obase, s)) || (rc = tmp.up(&d_pptr, plan.pptr, s)) ||
+      (rc = tmp.up(&d_pa, plan.pa, s)) || (rc = tmp.up(&d_pb, plan.pb, s)) ||
+      (rc = tmp.alloc(&cvals, (size_t)nvals)) ||
+      (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
+    return rc;
+  HIP_TRY(hipStreamSynchronize(s), "spgemm");
+  st.ms_symbolic = ms_since(t0);
+  sp.oi = d_oi;
+  sp.oj = d_oj;
+  sp.obase = d_obase;
+  sp.pptr = d_pptr;
+  sp.pa = d_pa;
+  sp.pb = d_pb;
+  sp.cvals = cvals;
+  sp.cnorm = cnorm;
+
+  // numeric stage, timed with events on the stream
+  const int max_b = n ? *std::max_element(b.begin(), b.end()) : 1;
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]), "hipEventCreate");
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return fail(VBCSR_EHIP, "hipEventCreate");
+  }
+  hipError_t e = hipEventRecord(ev[0], s);
+  if (e == hipSuccess) e = launch_spgemm_numeric(sp, max_b, s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_fail(e, "numeric stage");
+  st.ms_numeric = ms;
+
+  // final block-norm filter: drop computed blocks whose norm is below eps
+  t0 = clk::now();
+  std::vector<int64_t> crp(plan.row_ptr);
+  std::vector<int32_t> ccol(plan.oj);
+  const double *final_vals = cvals;
+  int64_t final_nvals = nvals;
+  if (eps > 0.0 && nC > 0) {
+    std::vector<double> nrm;
+    if ((rc = d2h(nrm, cnorm, (size_t)nC, s))) return rc;
+    HIP_TRY(hipStreamSynchronize(s), "spgemm");
+    std::vector<int64_t> sbase, dbase;
+    std::vector<int32_t> size;
+    ccol.clear();
+    int64_t c = 0, pos = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      crp[i] = (int64_t)ccol.size();
+      for (; c < plan.row_ptr[i + 1]; ++c) {
+        if (nrm[c] < eps) continue;
+        ccol.push_back(plan.oj[c]);
+        sbase.push_back(plan.obase[c]);
+        dbase.push_back(pos);
+        size.push_back((int32_t)(plan.obase[c + 1] - plan.obase[c]));
+        pos += size.back();
+      }
+    }
+    crp[n] = (int64_t)ccol.size();
+    if ((int64_t)ccol.size() < nC) {
+      double *packed = nullptr;
+      int64_t *d_sb = nullptr, *d_db = nullptr;
+      int32_t *d_sz = nullptr;
+      if ((rc = tmp.up(&d_sb, sbase, s)) || (rc = tmp.up(&d_db, dbase, s)) ||
+          (rc = tmp.up(&d_sz, size, s)) || (rc = tmp.alloc(&packed, (size_t)pos)))
+        return rc;
+      e = launch_gather_blocks(cvals, d_sb, d_db, d_sz, (int64_t)size.size(), packed, s);
+      if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
+      final_vals = packed;
+      final_nvals = pos;
+    }
+  }
+  st.nnzb = (int64_t)ccol.size();
+  st.ms_filter = ms_since(t0);
+
+  // C as an ordinary handle over the same atoms
+  t0 = clk::now();
+  vbcsr_plan_opts copts{};
+  if (opts) copts = *opts;
+  rc = create_impl(out, n, b.data(), crp.data(), ccol.empty() ? nullptr : ccol.data(), final_vals,
+                   true, final_nvals, VBCSR_FP64, &copts, stream);
+  if (rc) return rc;
+  st.ms_build = ms_since(t0);
+  if (stats) *stats = st;
+  return VBCSR_OK;
 }
 
 }  // extern "C"

@@ -66,4 +66,29 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                 int32_t row_order, HostPlan &plan);
 
+// Symbolic stage of the thresholded block product C = A B over one atom set
+// (host).  Candidates of row i are the columns j of the rows k of B with a
+// block (i, k) in A; each carries the bound U_ij = sum_k ||A_ik|| ||B_kj||
+// summed over k in A's stored order, and is kept unless U_ij < eps (with no
+// norms given every candidate is kept).  Kept columns are ascending per row.
+// The products of each kept block are listed in A's stored order of k.
+struct SpgemmPlan {
+  int64_t candidates = 0;        // distinct (i, j) reached through some k
+  std::vector<int64_t> row_ptr;  // n+1, over kept blocks
+  std::vector<int32_t> oi, oj;   // per kept block: row and column atom
+  std::vector<double> bound;     // per kept block: U_ij (0 when no norms)
+  std::vector<int64_t> obase;    // per kept block + 1: graph-order value offsets
+  std::vector<int64_t> pptr;     // per kept block + 1: product ranges
+  std::vector<int64_t> pa;       // per product: A page offset << 8 | b_k
+  std::vector<int64_t> pb;       // per product: B page offset
+  double flops = 0.0;            // sum over products of 2 b_i b_k b_j
+};
+
+// apos / bpos: page offset of every graph block of A (forward pages) and of
+// B (transposed pages).  an / bn: block norms, or both null.
+void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int32_t *aci,
+                     const int64_t *apos, const double *an, const int64_t *brp,
+                     const int32_t *bci, const int64_t *bpos, const double *bn, double eps,
+                     SpgemmPlan &out);
+
 }  // namespace vbcsr

@@ -1303,6 +1303,125 @@ hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t
   }
 }
 
+// ---------------------------------------------------------------------------
+// thresholded block product C = A B: numeric stage, block norms, unpacking
+// ---------------------------------------------------------------------------
+// One wave per output block C_ij (b_i x b_j): for each 16 x 16 output tile
+// it runs a matrix-core chain over all products of the block, K = b_k of
+// each product in steps of 4.  The A operand is A_ik from A's forward pages
+// (column-major b_i x b_k, lane (m, kq) reads row m, inner index kq of each
+// step: 16 consecutive values per quarter-wave), the B operand is B_kj from
+// B's transposed pages (which hold every block row-major, b_k x b_j: lane
+// (m, kq) reads inner index kq, column m, again 16 consecutive values).  Rows,
+// columns and inner indices past the block read as zero through the buffer
+// bounds, so padded lanes add exact zeros.  KS = inner steps of 4 held in
+// registers per product, ceil(largest b_k / 4).
+template <int KS>
+__global__ void __launch_bounds__(kThreads) k_spgemm(SpgemmParams P) {
+  const int64_t c = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
+  if (c >= P.nC) return;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  const int i = P.oi[c], j = P.oj[c];
+  const int bi = P.b[i], bj = P.b[j];
+  const int64_t p0 = P.pptr[c], p1 = P.pptr[c + 1];
+  double *out = P.cvals + P.obase[c];
+  constexpr uint32_t kOut = 0x80000000u;
+  double ss = 0.0;
+  for (int ti = 0; ti * 16 < bi; ++ti) {
+    for (int tj = 0; tj * 16 < bj; ++tj) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      const int ar = ti * 16 + m, bc = tj * 16 + m;
+      const uint32_t oa0 = ar < bi ? (uint32_t)(kq * bi + ar) * 8u : kOut;
+      const uint32_t ob0 = bc < bj ? (uint32_t)(kq * bj + bc) * 8u : kOut;
+      const uint32_t sa = 32u * (uint32_t)bi, sb = 32u * (uint32_t)bj;
+      for (int64_t q = p0; q < p1; ++q) {
+        const int64_t ak = P.pa[q];
+        const int bk = (int)(ak & 255);
+        const __amdgpu_buffer_rsrc_t ra =
+            panel_rsrc(P.avals + (ak >> 8), (uint32_t)(bi * bk) * 8u);
+        const __amdgpu_buffer_rsrc_t rb = panel_rsrc(P.bvals + P.pb[q], (uint32_t)(bk * bj) * 8u);
+        const int nks = (bk + 3) >> 2;
+        double a[KS], bb[KS];
+        // loads are unconditional (steps past b_k read zeros; a branch around
+        // a load would make the compiler wait for all loads in flight), the
+        // matrix instructions of those steps are skipped
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          a[s] = buf_load<double>(ra, oa0 + s * sa);
+          bb[s] = buf_load<double>(rb, ob0 + s * sb);
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+          if (s < nks) acc = mfma(a[s], bb[s], acc);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = ti * 16 + dst_row<double>(kq, e), col = tj * 16 + m;
+        if (r < bi && col < bj) {
+          out[(int64_t)r * bj + col] = acc[e];
+          ss = fma(acc[e], acc[e], ss);
+        }
+      }
+    }
+  }
+  if (P.cnorm) {
+    ss = wave_sum(ss);
+    if (lane == 0) P.cnorm[c] = sqrt(ss);
+  }
+}
+
+// Frobenius norm of every stored block from the forward pages (a block is a
+// contiguous run of b_i*b_j values there); one wave per block.
+__global__ void __launch_bounds__(kThreads) k_block_norms(const double *pages, const int64_t *pos,
+                                                          const int32_t *blk_row,
+                                                          const int32_t *col_idx,
+                                                          const int32_t *b, int64_t nnzb,
+                                                          double *out) {
+  const int64_t k = (int64_t)blockIdx.x * kWaves + wave_id();
+  if (k >= nnzb) return;
+  const int lane = threadIdx.x & 63;
+  const int sz = b[blk_row[k]] * b[col_idx[k]];
+  const double *v = pages + pos[k];
+  double s = 0.0;
+  for (int e = lane; e < sz; e += 64) s = fma(v[e], v[e], s);
+  s = wave_sum(s);
+  if (lane == 0) out[k] = sqrt(s);
+}
+
+// dst[dbase[t] + e] = src[sbase[t] + e] for e < size[t]; one wave per block.
+__global__ void __launch_bounds__(kThreads) k_gather_blocks(const double *src,
+                                                            const int64_t *sbase,
+                                                            const int64_t *dbase,
+                                                            const int32_t *size, int64_t nblk,
+                                                            double *dst) {
+  const int64_t t = (int64_t)blockIdx.x * kWaves + wave_id();
+  if (t >= nblk) return;
+  const int lane = threadIdx.x & 63;
+  const double *sp = src + sbase[t];
+  double *dp = dst + dbase[t];
+  for (int e = lane; e < size[t]; e += 64) dp[e] = sp[e];
+}
+
+// Forward pages -> graph order (each block row-major at gbase); one wave per
+// block.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_unpack(const T *pages, const int64_t *pos,
+                                                     const int32_t *blk_row,
+                                                     const int32_t *col_idx, const int32_t *b,
+                                                     const int64_t *gbase, int64_t nnzb, T *dst) {
+  const int64_t k = (int64_t)blockIdx.x * kWaves + wave_id();
+  if (k >= nnzb) return;
+  const int lane = threadIdx.x & 63;
+  const int bi = b[blk_row[k]], bj = b[col_idx[k]];
+  const T *sp = pages + pos[k];
+  T *dp = dst + gbase[k];
+  for (int e = lane; e < bi * bj; e += 64) {
+    const int p = e / bj, q = e - p * bj;
+    dp[e] = sp[(int64_t)q * bi + p];
+  }
+}
+
 }  // namespace
 
 int64_t product_workgroups(int64_t nrows) { return (nrows + kWaves - 1) / kWaves; }
@@ -1365,6 +1484,58 @@ hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t
                                   hipStream_t s) {
   if (nrhs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce, dim3((unsigned)nrhs), dim3(kThreads), 0, s, partial, nparts, nrhs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_spgemm_numeric(const SpgemmParams &p, int max_b, hipStream_t s) {
+  if (p.nC == 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.nC + kWaves - 1) / kWaves));
+  // registers per product cover ceil(max_b / 4) inner steps
+  switch ((max_b + 3) / 4) {
+#define VBCSR_SPGEMM_KS(n) \
+  case n: hipLaunchKernelGGL(k_spgemm<n>, grid, dim3(kThreads), 0, s, p); break;
+    VBCSR_SPGEMM_KS(1) VBCSR_SPGEMM_KS(2) VBCSR_SPGEMM_KS(3) VBCSR_SPGEMM_KS(4)
+    VBCSR_SPGEMM_KS(5) VBCSR_SPGEMM_KS(6) VBCSR_SPGEMM_KS(7) VBCSR_SPGEMM_KS(8)
+    VBCSR_SPGEMM_KS(9) VBCSR_SPGEMM_KS(10) VBCSR_SPGEMM_KS(11) VBCSR_SPGEMM_KS(12)
+    VBCSR_SPGEMM_KS(13) VBCSR_SPGEMM_KS(14) VBCSR_SPGEMM_KS(15) VBCSR_SPGEMM_KS(16)
+#undef VBCSR_SPGEMM_KS
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,
+                              const int32_t *col_idx, const int32_t *b, int64_t nnzb, double *out,
+                              hipStream_t s) {
+  if (nnzb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((nnzb + kWaves - 1) / kWaves));
+  hipLaunchKernelGGL(k_block_norms, grid, dim3(kThreads), 0, s, pages, pos, blk_row, col_idx, b,
+                     nnzb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_blocks(const double *src, const int64_t *sbase, const int64_t *dbase,
+                                const int32_t *size, int64_t nblk, double *dst, hipStream_t s) {
+  if (nblk == 0) return hipSuccess;
+  const dim3 grid((unsigned)((nblk + kWaves - 1) / kWaves));
+  hipLaunchKernelGGL(k_gather_blocks, grid, dim3(kThreads), 0, s, src, sbase, dbase, size, nblk,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const void *pages, int elem_bytes, const int64_t *pos,
+                         const int32_t *blk_row, const int32_t *col_idx, const int32_t *b,
+                         const int64_t *gbase, int64_t nnzb, void *dst, hipStream_t s) {
+  if (nnzb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((nnzb + kWaves - 1) / kWaves));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_unpack<double>, grid, dim3(kThreads), 0, s,
+                       static_cast<const double *>(pages), pos, blk_row, col_idx, b, gbase, nnzb,
+                       static_cast<double *>(dst));
+  else
+    hipLaunchKernelGGL(k_unpack<float>, grid, dim3(kThreads), 0, s,
+                       static_cast<const float *>(pages), pos, blk_row, col_idx, b, gbase, nnzb,
+                       static_cast<float *>(dst));
   return hipGetLastError();
 }
 

@@ -93,4 +93,39 @@ int64_t coldot_chunks(int64_t nrows);
 hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t nrhs, double *out,
                                   hipStream_t s);
 
+// Numeric stage of the thresholded block product C = A B (one wave per
+// output block).  Output block c (row atom oi[c], column atom oj[c]) is the
+// sum over its products q in [pptr[c], pptr[c+1]) of A_ik B_kj, with A_ik at
+// page offset pa[q] >> 8 of A's forward pages (column-major b_i x b_k,
+// b_k = pa[q] & 255) and B_kj at page offset pb[q] of B's transposed pages
+// (row-major b_k x b_j).  The block is written row-major at cvals + obase[c]
+// and, when cnorm is set, its Frobenius norm to cnorm[c].
+struct SpgemmParams {
+  const double *avals;
+  const double *bvals;
+  const int32_t *b;
+  const int32_t *oi;
+  const int32_t *oj;
+  const int64_t *obase;
+  const int64_t *pptr;
+  const int64_t *pa;
+  const int64_t *pb;
+  int64_t nC;
+  double *cvals;
+  double *cnorm;
+};
+hipError_t launch_spgemm_numeric(const SpgemmParams &p, int max_b, hipStream_t s);
+
+// out[k] = Frobenius norm of graph block k, read from forward pages at pos[k].
+hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,
+                              const int32_t *col_idx, const int32_t *b, int64_t nnzb, double *out,
+                              hipStream_t s);
+// dst[dbase[t] + e] = src[sbase[t] + e], e < size[t], t < nblk.
+hipError_t launch_gather_blocks(const double *src, const int64_t *sbase, const int64_t *dbase,
+                                const int32_t *size, int64_t nblk, double *dst, hipStream_t s);
+// Forward pages (elem_bytes 8 or 4) -> graph-order row-major blocks at gbase.
+hipError_t launch_unpack(const void *pages, int elem_bytes, const int64_t *pos,
+                         const int32_t *blk_row, const int32_t *col_idx, const int32_t *b,
+                         const int64_t *gbase, int64_t nnzb, void *dst, hipStream_t s);
+
 }  // namespace vbcsr

@@ -77,6 +77,25 @@ class Matrix:
             self.set_values(dev_vals)
 
     @classmethod
+    def _adopt(cls, h, n_atoms: int, prec: str = "fp64"):
+        """Wrap a handle the library created (the block product's result)."""
+        self = cls.__new__(cls)
+        self._h = h
+        self.prec, self.dtype = prec, _TORCH_DTYPE[prec]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        inf = self.info()
+        self.n, self.N, self.n_values = int(n_atoms), inf["N"], inf["n_values"]
+        b = np.empty(self.n, np.int32)
+        rp = np.empty(self.n + 1, np.int64)
+        ci = np.empty(max(inf["nnzb"], 1), np.int32)
+        check(_lib.load().vbcsr_get_structure(self._h, b.ctypes.data, rp.ctypes.data,
+                                              ci.ctypes.data))
+        self.block_sizes, self.row_ptr, self.col_idx = b, rp, ci[:inf["nnzb"]]
+        Matrix._stamps += 1
+        self._stamp = Matrix._stamps
+        return self
+
+    @classmethod
     def from_operator(cls, op, prec="fp64", values=None, **kw):
         """Build from a ``workloads.Operator``-like object (b, row_ptr, col_idx, values)."""
         return cls(op.b, op.row_ptr, op.col_idx, op.values if values is None else values,
@@ -115,6 +134,26 @@ class Matrix:
                                      ctypes.byref(nval), ctypes.byref(nsh)))
         return {"N": n_rows.value, "nnzb": nnzb.value, "n_values": nval.value,
                 "n_shapes": nsh.value}
+
+    def values(self):
+        """Block values in graph order (each block row-major), a device tensor."""
+        out = torch.empty(self.n_values, dtype=self.dtype, device=self.device)
+        check(_lib.load().vbcsr_get_values(self._h, _ptr(out), 0 if self.prec == "fp64" else 1,
+                                           _stream()))
+        return out
+
+    def spgemm(self, B: "Matrix", eps: float = 0.0, path: str = "auto", nrhs_tile: int = 0,
+               row_order: str = "auto"):
+        """Thresholded block product ``C = A B`` (section 3.2, equations 2 and 3).
+
+        Returns ``(C, stats)``: C is a new FP64 ``Matrix`` over the same atoms;
+        ``stats`` holds the counts and phase times of the call."""
+        opts = _lib.PlanOpts(0, int(nrhs_tile), _lib.PATH[path], _lib.ORDER[row_order])
+        st = _lib.SpgemmStats()
+        h = ctypes.c_void_p()
+        check(_lib.load().vbcsr_spgemm(ctypes.byref(h), self._h, B._h, float(eps),
+                                       ctypes.byref(opts), ctypes.byref(st), _stream()))
+        return Matrix._adopt(h, self.n), {f: getattr(st, f) for f, _ in _lib.SpgemmStats._fields_}
 
     # -- values -------------------------------------------------------------
     def set_values(self, values):

@@ -227,6 +227,12 @@ def test_null_handle_and_bad_arguments(lib):
     assert lib.vbcsr_sddmm(None, None, 1, None, 1, 1, None, None) == _lib.VBCSR_EINVAL
     assert lib.vbcsr_set_values(None, None, 0, 0, None) == _lib.VBCSR_EINVAL
     assert lib.vbcsr_info(None, None, None, None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_get_structure(None, None, None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_get_values(None, None, 0, None) == _lib.VBCSR_EINVAL
+    out = ctypes.c_void_p(1)
+    assert lib.vbcsr_spgemm(ctypes.byref(out), None, None, 0.0, None, None, None) == _lib.VBCSR_EINVAL
+    assert out.value is None
+    assert lib.vbcsr_spgemm(None, None, None, 0.0, None, None, None) == _lib.VBCSR_EINVAL
     lib.vbcsr_destroy(None)
     h = ctypes.c_void_p()
     b = np.array([1], np.int32)
