@@ -328,12 +328,13 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     } else {
       const size_t es = prec == VBCSR_FP64 ? 8 : 4;
       char *p = nullptr;
-      if ((rc = alloc_into(A, &p, es * (size_t)P.n_values))) return bail(rc);
+      // kPageSlack values after the pages: 16-byte reads that start on a
+      // block's last value stay inside the allocation
+      const size_t bytes = es * (size_t)(P.n_values + kPageSlack);
+      if ((rc = alloc_into(A, &p, bytes))) return bail(rc);
       // the padding after each panel must read as zero
-      if (P.n_values) {
-        hipError_t e = hipMemsetAsync(p, 0, es * (size_t)P.n_values, s);
-        if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
-      }
+      hipError_t e = hipMemsetAsync(p, 0, bytes, s);
+      if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
       D.vals = p;
     }
   }
@@ -757,8 +758,8 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if ((rc = d2h(b, A->b, n, s)) || (rc = d2h(bb, B->b, n, s)) ||
       (rc = d2h(arp, A->row_ptr, (size_t)n + 1, s)) || (rc = d2h(brp, B->row_ptr, (size_t)n + 1, s)) ||
       (rc = d2h(aci, A->col_idx, A->nnzb, s)) || (rc = d2h(bci, B->col_idx, B->nnzb, s)) ||
-      (rc = d2h(apos, A->dir[0].blk_pos, A->nnzb, s)) ||
-      (rc = d2h(bpos, B->dir[1].blk_pos, B->nnzb, s)))
+      (rc = d2h(apos, A->dir[1].blk_pos, A->nnzb, s)) ||
+      (rc = d2h(bpos, B->dir[0].blk_pos, B->nnzb, s)))
     return rc;
   // block norms, needed only to compare with a positive threshold
   std::vector<double> an, bn;
@@ -790,17 +791,29 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   st.kept_symbolic = nC;
   st.products = (int64_t)plan.pa.size();
   st.flops = plan.flops;
+  // output blocks grouped by tile class (one launch each)
+  std::vector<int32_t> order((size_t)nC);
+  int64_t cls_begin[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t c = 0; c < nC; ++c) cls_begin[spgemm_class(b[plan.oi[c]], b[plan.oj[c]]) + 1]++;
+  for (int k = 0; k < 5; ++k) cls_begin[k + 1] += cls_begin[k];
+  {
+    int64_t fill[5];
+    std::copy(cls_begin, cls_begin + 5, fill);
+    for (int64_t c = 0; c < nC; ++c)
+      order[fill[spgemm_class(b[plan.oi[c]], b[plan.oj[c]])]++] = (int32_t)c;
+  }
   SpgemmParams sp{};
-  sp.avals = static_cast<const double *>(A->dir[0].vals);
-  sp.bvals = static_cast<const double *>(B->dir[1].vals);
+  sp.avals = static_cast<const double *>(A->dir[1].vals);
+  sp.bvals = static_cast<const double *>(B->dir[0].vals);
   sp.b = A->b;
-  sp.nC = nC;
-  int32_t *d_oi = nullptr, *d_oj = nullptr;
+
+  int32_t *d_oi = nullptr, *d_oj = nullptr, *d_order = nullptr;
   int64_t *d_obase = nullptr, *d_pptr = nullptr, *d_pa = nullptr, *d_pb = nullptr;
   double *cvals = nullptr, *cnorm = nullptr;
   if ((rc = tmp.up(&d_oi, plan.oi, s)) || (rc = tmp.up(&d_oj, plan.oj, s)) ||
       (rc = tmp.up(&d_obase, plan.obase, s)) || (rc = tmp.up(&d_pptr, plan.pptr, s)) ||
       (rc = tmp.up(&d_pa, plan.pa, s)) || (rc = tmp.up(&d_pb, plan.pb, s)) ||
+      (rc = tmp.up(&d_order, order, s)) ||
       (rc = tmp.alloc(&cvals, (size_t)nvals)) ||
       (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
     return rc;
@@ -824,7 +837,12 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
     return fail(VBCSR_EHIP, "hipEventCreate");
   }
   hipError_t e = hipEventRecord(ev[0], s);
-  if (e == hipSuccess) e = launch_spgemm_numeric(sp, max_b, s);
+  for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+    SpgemmParams pk = sp;
+    pk.order = d_order + cls_begin[k];
+    pk.count = cls_begin[k + 1] - cls_begin[k];
+    e = launch_spgemm_numeric(pk, k, max_b, s);
+  }
   if (e == hipSuccess) e = hipEventRecord(ev[1], s);
   if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
   float ms = 0.f;

@@ -30,8 +30,10 @@ struct RowDesc {
 static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 
 // Value pages: every panel starts at a multiple of this many values; the
-// gap after a panel holds zeros.
+// gap after a panel holds zeros.  FP64/FP32 pages are followed by
+// kPageSlack zero values.
 constexpr int64_t kPanelAlign = 4;
+constexpr int64_t kPageSlack = 2;
 
 struct DirPlan {
   std::vector<RowDesc> rows;     // one per atom, in processing order
@@ -79,13 +81,14 @@ struct SpgemmPlan {
   std::vector<double> bound;     // per kept block: U_ij (0 when no norms)
   std::vector<int64_t> obase;    // per kept block + 1: graph-order value offsets
   std::vector<int64_t> pptr;     // per kept block + 1: product ranges
-  std::vector<int64_t> pa;       // per product: A page offset << 8 | b_k
-  std::vector<int64_t> pb;       // per product: B page offset
+  std::vector<int64_t> pa;       // per product: apos of A_ik << 8 | b_k
+  std::vector<int64_t> pb;       // per product: bpos of B_kj
   double flops = 0.0;            // sum over products of 2 b_i b_k b_j
 };
 
-// apos / bpos: page offset of every graph block of A (forward pages) and of
-// B (transposed pages).  an / bn: block norms, or both null.
+// apos / bpos: page offset of every graph block of A and of B (the device
+// reads A_ik row-major from A's transposed pages and B_kj column-major from
+// B's forward pages).  an / bn: block norms, or both null.
 void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int32_t *aci,
                      const int64_t *apos, const double *an, const int64_t *brp,
                      const int32_t *bci, const int64_t *bpos, const double *bn, double eps,

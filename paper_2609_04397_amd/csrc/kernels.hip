@@ -1306,68 +1306,115 @@ hipError_t launch_spmm_t(const FwdParams<T> &p, Kind kind, int tile, hipStream_t
 // ---------------------------------------------------------------------------
 // thresholded block product C = A B: numeric stage, block norms, unpacking
 // ---------------------------------------------------------------------------
-// One wave per output block C_ij (b_i x b_j): for each 16 x 16 output tile
-// it runs a matrix-core chain over all products of the block, K = b_k of
-// each product in steps of 4.  The A operand is A_ik from A's forward pages
-// (column-major b_i x b_k, lane (m, kq) reads row m, inner index kq of each
-// step: 16 consecutive values per quarter-wave), the B operand is B_kj from
-// B's transposed pages (which hold every block row-major, b_k x b_j: lane
-// (m, kq) reads inner index kq, column m, again 16 consecutive values).  Rows,
-// columns and inner indices past the block read as zero through the buffer
-// bounds, so padded lanes add exact zeros.  KS = inner steps of 4 held in
-// registers per product, ceil(largest b_k / 4).
-template <int KS>
-__global__ void __launch_bounds__(kThreads) k_spgemm(SpgemmParams P) {
-  const int64_t c = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
-  if (c >= P.nC) return;
+// One wave per output block C_ij (b_i x b_j, 16 x 16 output tiles): a
+// matrix-core chain over all products A_ik B_kj of the block, every tile of
+// the block accumulated in the same pass so that each operand load serves
+// all tiles it belongs to.  The vector-memory instruction count bounds this
+// kernel (as the products), so each lane loads 16 bytes: two consecutive
+// inner indices k0 = 8t + 2kq and k0 + 1 of its row of A_ik (row-major, from
+// A's transposed pages, which hold every block row-major) and of its column
+// of B_kj (column-major, from B's forward pages).  Step pair t then feeds two
+// matrix instructions, the first over k = 8t + {0, 2, 4, 6}, the second over
+// 8t + {1, 3, 5, 7}; both operands use the same k per lane, so the sum is the
+// same.  Lanes past the block (row, column or k0 >= b_k) read zeros through
+// the buffer bounds; when k0 + 1 == b_k the second value belongs to the next
+// row or column (or the slack after the pages) and is replaced by zero.
+// Matrix instructions whose k are all past b_k are skipped.
+__device__ __forceinline__ double2 pair_load(__amdgpu_buffer_rsrc_t r, uint32_t off,
+                                             bool second) {
+  double2 v = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+  v.y = second ? v.y : 0.0;
+  return v;
+}
+
+// Tiles [ti0, ti0 + TI) x [tj0, tj0 + TJ) of output block c.
+template <int KS2, int TI, int TJ>
+__device__ __forceinline__ void spgemm_tiles(const SpgemmParams &P, int64_t c, int bi, int bj,
+                                             int ti0, int tj0, double &ss) {
   const int lane = threadIdx.x & 63;
   const int m = lane & 15, kq = lane >> 4;
-  const int i = P.oi[c], j = P.oj[c];
-  const int bi = P.b[i], bj = P.b[j];
-  const int64_t p0 = P.pptr[c], p1 = P.pptr[c + 1];
-  double *out = P.cvals + P.obase[c];
+  const int64_t p0 = P.pptr[c];
+  const int np = (int)(P.pptr[c + 1] - p0);
+  const int64_t *__restrict__ pa = P.pa + p0;
+  const int64_t *__restrict__ pb = P.pb + p0;
   constexpr uint32_t kOut = 0x80000000u;
-  double ss = 0.0;
-  for (int ti = 0; ti * 16 < bi; ++ti) {
-    for (int tj = 0; tj * 16 < bj; ++tj) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-      const int ar = ti * 16 + m, bc = tj * 16 + m;
-      const uint32_t oa0 = ar < bi ? (uint32_t)(kq * bi + ar) * 8u : kOut;
-      const uint32_t ob0 = bc < bj ? (uint32_t)(kq * bj + bc) * 8u : kOut;
-      const uint32_t sa = 32u * (uint32_t)bi, sb = 32u * (uint32_t)bj;
-      for (int64_t q = p0; q < p1; ++q) {
-        const int64_t ak = P.pa[q];
-        const int bk = (int)(ak & 255);
-        const __amdgpu_buffer_rsrc_t ra =
-            panel_rsrc(P.avals + (ak >> 8), (uint32_t)(bi * bk) * 8u);
-        const __amdgpu_buffer_rsrc_t rb = panel_rsrc(P.bvals + P.pb[q], (uint32_t)(bk * bj) * 8u);
-        const int nks = (bk + 3) >> 2;
-        double a[KS], bb[KS];
-        // loads are unconditional (steps past b_k read zeros; a branch around
-        // a load would make the compiler wait for all loads in flight), the
-        // matrix instructions of those steps are skipped
+  v4d acc[TI][TJ];
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          a[s] = buf_load<double>(ra, oa0 + s * sa);
-          bb[s] = buf_load<double>(rb, ob0 + s * sb);
-        }
+  for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
-          if (s < nks) acc = mfma(a[s], bb[s], acc);
+    for (int tj = 0; tj < TJ; ++tj) acc[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < np; ++q) {
+    const int64_t ak = pa[q];
+    const int bk = (int)(ak & 255);
+    // one value of slack past each block: the pair load of k0 = b_k - 1 on
+    // the last row reads it (and discards it)
+    const __amdgpu_buffer_rsrc_t ra =
+        panel_rsrc(P.avals + (ak >> 8), (uint32_t)(bi * bk + 1) * 8u);
+    const __amdgpu_buffer_rsrc_t rb = panel_rsrc(P.bvals + pb[q], (uint32_t)(bk * bj + 1) * 8u);
+    double2 av[TI][KS2], bv[TJ][KS2];
+#pragma unroll
+    for (int t = 0; t < KS2; ++t) {
+      const int k0 = 8 * t + 2 * kq;
+      const bool kin = k0 < bk, k2 = k0 + 1 < bk;
+#pragma unroll
+      for (int ti = 0; ti < TI; ++ti) {
+        const int row = (ti0 + ti) * 16 + m;
+        av[ti][t] = pair_load(ra, row < bi && kin ? (uint32_t)(row * bk + k0) * 8u : kOut, k2);
       }
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = ti * 16 + dst_row<double>(kq, e), col = tj * 16 + m;
-        if (r < bi && col < bj) {
-          out[(int64_t)r * bj + col] = acc[e];
-          ss = fma(acc[e], acc[e], ss);
+      for (int tj = 0; tj < TJ; ++tj) {
+        const int col = (tj0 + tj) * 16 + m;
+        bv[tj][t] = pair_load(rb, col < bj && kin ? (uint32_t)(col * bk + k0) * 8u : kOut, k2);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < KS2; ++t) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (8 * t + h < bk) {
+#pragma unroll
+          for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+            for (int tj = 0; tj < TJ; ++tj)
+              acc[ti][tj] = mfma(h ? av[ti][t].y : av[ti][t].x, h ? bv[tj][t].y : bv[tj][t].x,
+                                 acc[ti][tj]);
         }
       }
     }
   }
+  double *out = P.cvals + P.obase[c];
+#pragma unroll
+  for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = (ti0 + ti) * 16 + dst_row<double>(kq, e), col = (tj0 + tj) * 16 + m;
+        if (r < bi && col < bj) {
+          out[(int64_t)r * bj + col] = acc[ti][tj][e];
+          ss = fma(acc[ti][tj][e], acc[ti][tj][e], ss);
+        }
+      }
+}
+
+// Output blocks P.order[0 .. P.count) of one tile class: TI x TJ tiles of
+// 16 x 16, or (TI = TJ = 0) any size, one tile at a time.
+template <int KS2, int TI, int TJ>
+__global__ void __launch_bounds__(kThreads) k_spgemm(SpgemmParams P) {
+  const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
+  if (w >= P.count) return;
+  const int64_t c = P.order[w];
+  const int bi = P.b[P.oi[c]], bj = P.b[P.oj[c]];
+  double ss = 0.0;
+  if constexpr (TI > 0) {
+    spgemm_tiles<KS2, TI, TJ>(P, c, bi, bj, 0, 0, ss);
+  } else {
+    for (int ti = 0; ti * 16 < bi; ++ti)
+      for (int tj = 0; tj * 16 < bj; ++tj) spgemm_tiles<KS2, 1, 1>(P, c, bi, bj, ti, tj, ss);
+  }
   if (P.cnorm) {
     ss = wave_sum(ss);
-    if (lane == 0) P.cnorm[c] = sqrt(ss);
+    if ((threadIdx.x & 63) == 0) P.cnorm[c] = sqrt(ss);
   }
 }
 
@@ -1487,21 +1534,27 @@ hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_spgemm_numeric(const SpgemmParams &p, int max_b, hipStream_t s) {
-  if (p.nC == 0) return hipSuccess;
-  const dim3 grid((unsigned)((p.nC + kWaves - 1) / kWaves));
-  // registers per product cover ceil(max_b / 4) inner steps
-  switch ((max_b + 3) / 4) {
-#define VBCSR_SPGEMM_KS(n) \
-  case n: hipLaunchKernelGGL(k_spgemm<n>, grid, dim3(kThreads), 0, s, p); break;
-    VBCSR_SPGEMM_KS(1) VBCSR_SPGEMM_KS(2) VBCSR_SPGEMM_KS(3) VBCSR_SPGEMM_KS(4)
-    VBCSR_SPGEMM_KS(5) VBCSR_SPGEMM_KS(6) VBCSR_SPGEMM_KS(7) VBCSR_SPGEMM_KS(8)
-    VBCSR_SPGEMM_KS(9) VBCSR_SPGEMM_KS(10) VBCSR_SPGEMM_KS(11) VBCSR_SPGEMM_KS(12)
-    VBCSR_SPGEMM_KS(13) VBCSR_SPGEMM_KS(14) VBCSR_SPGEMM_KS(15) VBCSR_SPGEMM_KS(16)
-#undef VBCSR_SPGEMM_KS
-    default: return hipErrorInvalidValue;
+template <int KS2>
+hipError_t launch_spgemm_ks(const SpgemmParams &p, int cls, dim3 grid, hipStream_t s) {
+  switch (cls) {
+    case 0: hipLaunchKernelGGL((k_spgemm<KS2, 1, 1>), grid, dim3(kThreads), 0, s, p); break;
+    case 1: hipLaunchKernelGGL((k_spgemm<KS2, 1, 2>), grid, dim3(kThreads), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((k_spgemm<KS2, 2, 1>), grid, dim3(kThreads), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((k_spgemm<KS2, 2, 2>), grid, dim3(kThreads), 0, s, p); break;
+    default: hipLaunchKernelGGL((k_spgemm<KS2, 0, 0>), grid, dim3(kThreads), 0, s, p); break;
   }
   return hipGetLastError();
+}
+
+hipError_t launch_spgemm_numeric(const SpgemmParams &p, int cls, int max_b, hipStream_t s) {
+  if (p.count == 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.count + kWaves - 1) / kWaves));
+  // pairs of inner indices held per product: ceil(max_b / 8)
+  if (max_b <= 8) return launch_spgemm_ks<1>(p, cls, grid, s);
+  if (max_b <= 16) return launch_spgemm_ks<2>(p, cls, grid, s);
+  if (max_b <= 24) return launch_spgemm_ks<3>(p, cls, grid, s);
+  if (max_b <= 32) return launch_spgemm_ks<4>(p, cls, grid, s);
+  return launch_spgemm_ks<8>(p, cls, grid, s);
 }
 
 hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,

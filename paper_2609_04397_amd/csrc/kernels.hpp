@@ -96,10 +96,11 @@ hipError_t launch_reduce_partials(const double *partial, int64_t nparts, int32_t
 // Numeric stage of the thresholded block product C = A B (one wave per
 // output block).  Output block c (row atom oi[c], column atom oj[c]) is the
 // sum over its products q in [pptr[c], pptr[c+1]) of A_ik B_kj, with A_ik at
-// page offset pa[q] >> 8 of A's forward pages (column-major b_i x b_k,
-// b_k = pa[q] & 255) and B_kj at page offset pb[q] of B's transposed pages
-// (row-major b_k x b_j).  The block is written row-major at cvals + obase[c]
-// and, when cnorm is set, its Frobenius norm to cnorm[c].
+// page offset pa[q] >> 8 of A's transposed pages (row-major b_i x b_k,
+// b_k = pa[q] & 255) and B_kj at page offset pb[q] of B's forward pages
+// (column-major b_k x b_j).  The block is written row-major at
+// cvals + obase[c] and, when cnorm is set, its Frobenius norm to cnorm[c].
+// A launch covers the blocks order[0 .. count) of one tile class.
 struct SpgemmParams {
   const double *avals;
   const double *bvals;
@@ -110,11 +111,18 @@ struct SpgemmParams {
   const int64_t *pptr;
   const int64_t *pa;
   const int64_t *pb;
-  int64_t nC;
+  const int32_t *order;
+  int64_t count;
   double *cvals;
   double *cnorm;
 };
-hipError_t launch_spgemm_numeric(const SpgemmParams &p, int max_b, hipStream_t s);
+// Tile class of a b_i x b_j block: 0 (1x1 tiles of 16), 1 (1x2), 2 (2x1),
+// 3 (2x2), 4 (anything larger).
+inline int spgemm_class(int bi, int bj) {
+  const int ti = (bi + 15) / 16, tj = (bj + 15) / 16;
+  return ti > 2 || tj > 2 ? 4 : (ti - 1) * 2 + (tj - 1);
+}
+hipError_t launch_spgemm_numeric(const SpgemmParams &p, int cls, int max_b, hipStream_t s);
 
 // out[k] = Frobenius norm of graph block k, read from forward pages at pos[k].
 hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,
