@@ -74,6 +74,8 @@ def parse():
                     help="also run a plain 1 GiB device copy (scale for traffic counters)")
     ap.add_argument("--sweep", default="",
                     help="write an nrhs sweep over the workloads (JSON lines) to this file")
+    ap.add_argument("--spgemm", action="store_true",
+                    help="only run the block product records (G1, A A) and print them")
     return ap.parse_args()
 
 
@@ -82,6 +84,10 @@ def main():
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
+    if args.spgemm:
+        for rec in spgemm_records(with_cpu=not args.no_cpu):
+            print(json.dumps(rec), flush=True)
+        return
     import torch
     from paper_2609_04397_amd import Matrix
     from workloads.core import sc_lattice, inf_norm_scale, scaled
@@ -375,7 +381,65 @@ def run_sweep(path):
         emit(dict(size, op="cheb degree 64", prec=prec, nrhs=64, ms=round(t_plain, 4),
                   doubled_ms=round(t_dbl, 4), speedup=round(t_plain / t_dbl, 3)))
         A.close()
+    del op4, vec4
+    for rec in spgemm_records(with_cpu=True):
+        emit(rec)
     out.close()
+
+
+def spgemm_records(with_cpu=True):
+    """Thresholded block product A A of the G1 operator (11,520 atoms, b in
+    9..20, 502 MiB of FP64 values) at eps = 0 and eps = 1 (which drops about
+    60 % of the product's blocks): whole-call time, its phases, and the
+    numeric kernel's FP64 matrix-core rate.  The CPU oracle (one thread) is
+    timed on 200 sampled block rows for comparison."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads.configs import make_operator
+
+    op = make_operator("G1")
+    size = {"workload": "G1", "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz}
+    A = Matrix.from_operator(op)
+    recs = []
+    for eps in (0.0, 1.0):
+        runs = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            C, st = A.spgemm(A, eps)
+            torch.cuda.synchronize()
+            runs.append(((time.perf_counter() - t0) * 1e3, st))
+            C.close()
+        runs = runs[1:]  # first call warms up
+        tot = float(np.median([r[0] for r in runs]))
+        st = sorted(runs, key=lambda r: r[1]["ms_numeric"])[len(runs) // 2][1]
+        tf = st["flops"] / (st["ms_numeric"] * 1e-3) / 1e12
+        rec = dict(size, op="spgemm A A", prec="fp64", nrhs=None, eps=eps, ms=round(tot, 3),
+                   numeric_ms=round(st["ms_numeric"], 4),
+                   phases_ms={k[3:]: round(st[k], 3) for k in st if k.startswith("ms_")},
+                   candidates=st["candidates"], kept_symbolic=st["kept_symbolic"],
+                   nnzb_C=st["nnzb"], products=st["products"], gflop=round(st["flops"] / 1e9, 3),
+                   numeric_tflops=round(tf, 3), mfma_frac=round(tf / PEAK_TFLOPS["fp64"], 4))
+        recs.append(rec)
+    A.close()
+    if with_cpu:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        import oracle
+        rows = np.random.default_rng(0).choice(op.n, 200, replace=False)
+        fl = 0.0
+        for i in rows:
+            ks = op.col_idx[op.row_ptr[i]:op.row_ptr[i + 1]]
+            for k in ks:
+                js = op.col_idx[op.row_ptr[k]:op.row_ptr[k + 1]]
+                fl += 2.0 * op.b[i] * op.b[k] * float(op.b[js].sum())
+        t0 = time.perf_counter()
+        oracle.spgemm(op, op, 0.0, rows=rows)
+        dt = time.perf_counter() - t0
+        recs.append(dict(size, op="spgemm A A oracle (1 thread, 200 rows)", prec="fp64", nrhs=None,
+                         eps=0.0, ms=round(dt * 1e3, 2), gflop=round(fl / 1e9, 4),
+                         gflops=round(fl / dt / 1e9, 3),
+                         full_product_s_est=round(dt * op.n / 200, 2)))
+    return recs
 
 
 def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, budget_s=12.0):

@@ -127,13 +127,12 @@ def test_spgemm_random(case, mode):
 
 @pytest.mark.parametrize("name,scale", [("C1", 1.0), ("C5", 0.01), ("C2", 0.05), ("G1", 0.03),
                                         ("C3", 0.002)])
-@pytest.mark.parametrize("eps", [0.0, 1e-2])
+@pytest.mark.parametrize("eps", [0.0, 0.5])
 def test_spgemm_workloads(name, scale, eps):
     op = make_operator(name, scale)
     print("case spgemm", name, scale, eps, op.n, flush=True)
     Am, Bm, C, st, vals = gpu_product(op, op, eps)
     compare(op, op, eps, C, vals)
-    fl = 0.0
     assert st["products"] > 0 and st["flops"] > 0
 
 
@@ -202,7 +201,7 @@ def test_get_values_roundtrip():
         assert np.array_equal(b, op.b) and np.array_equal(rp, op.row_ptr)
 
 
-@pytest.mark.parametrize("eps", [0.0, 1e-3])
+@pytest.mark.parametrize("eps", [0.0, 1.0])
 def test_spgemm_g1_full_size_sampled(eps):
     """The benchmarked product (G1, about 500 MiB of FP64 values, A A) on
     sampled block rows, including the first and last."""
@@ -212,4 +211,6 @@ def test_spgemm_g1_full_size_sampled(eps):
     rng = np.random.default_rng(11)
     rows = np.unique(np.concatenate([[0, op.n - 1], rng.choice(op.n, 60, replace=False)]))
     assert compare(op, op, eps, C, vals, rows=rows) > 0
+    if eps > 0:   # the threshold acts in both stages at this size
+        assert st["kept_symbolic"] < st["candidates"] and st["nnzb"] < st["kept_symbolic"]
     print("G1 stats", st, flush=True)
