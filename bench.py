@@ -76,6 +76,8 @@ def parse():
                     help="write an nrhs sweep over the workloads (JSON lines) to this file")
     ap.add_argument("--spgemm", action="store_true",
                     help="only run the block product records (G1, A A) and print them")
+    ap.add_argument("--kpm", action="store_true",
+                    help="only run the KPM density-of-states records and print them")
     return ap.parse_args()
 
 
@@ -84,8 +86,10 @@ def main():
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
-    if args.spgemm:
-        for rec in spgemm_records(with_cpu=not args.no_cpu):
+    if args.spgemm or args.kpm:
+        recs = (spgemm_records(with_cpu=not args.no_cpu) if args.spgemm else []) + \
+            (kpm_records(with_cpu=not args.no_cpu) if args.kpm else [])
+        for rec in recs:
             print(json.dumps(rec), flush=True)
         return
     import torch
@@ -384,7 +388,51 @@ def run_sweep(path):
     del op4, vec4
     for rec in spgemm_records(with_cpu=True):
         emit(rec)
+    for rec in kpm_records(with_cpu=True):
+        emit(rec)
     out.close()
+
+
+def kpm_records(with_cpu=True):
+    """Density of states from 147,456 Chebyshev moments (the paper's count)
+    on 300,000 points of the scaled axis, Jackson damping.  The kernel takes
+    one FMA and one add per moment and point (Clenshaw), so its ceiling is
+    the FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz / 2
+    instructions = 19.66e12 point-moments per second.  The oracle (direct
+    cos(k arccos x) sums, numpy) is timed on 64 of the points."""
+    import torch
+    from paper_2609_04397_amd import kpm
+
+    M, P = 147456, 300000
+    lam = np.random.default_rng(5).uniform(-0.9, 0.9, 64)
+    mu = np.empty(M)
+    t0, t1 = np.ones_like(lam), lam.copy()
+    mu[0], mu[1] = 1.0, t1.mean()
+    for k in range(2, M):
+        t0, t1 = t1, 2 * lam * t1 - t0
+        mu[k] = t1.mean()
+    dev = torch.device("cuda", 0)
+    mud = torch.from_numpy(mu).to(dev)
+    x = torch.linspace(-0.99, 0.99, P, dtype=torch.float64, device=dev)
+    work = torch.empty(M, dtype=torch.float64, device=dev)
+    ms = _time_call(lambda: kpm.dos(mud, x, "jackson", work=work))
+    rate = (M - 1) * P / (ms * 1e-3)
+    peak = 256 * 4 * 16 * 2.4e9 / 2
+    recs = [{"workload": "KPM DOS", "op": "kpm_dos jackson", "prec": "fp64", "nrhs": None,
+             "n_moments": M, "n_points": P, "ms": round(ms, 4),
+             "point_moments_per_s": round(rate, 1), "alu_frac": round(rate / peak, 4),
+             "alu_peak_point_moments_per_s": peak}]
+    if with_cpu:
+        sys.path.insert(0, os.path.join(ROOT, "tests"))
+        from oracle import kpm as okpm
+        xs = np.linspace(-0.99, 0.99, 64)
+        t = time.perf_counter()
+        okpm.dos(mu, xs)
+        dt = time.perf_counter() - t
+        recs.append({"workload": "KPM DOS", "op": "kpm_dos oracle (numpy, 64 points)",
+                     "prec": "fp64", "nrhs": None, "n_moments": M, "n_points": 64,
+                     "ms": round(dt * 1e3, 2), "point_moments_per_s": round(M * 64 / dt, 1)})
+    return recs
 
 
 def spgemm_records(with_cpu=True):

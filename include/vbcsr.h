@@ -302,6 +302,51 @@ typedef struct {
 int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double eps,
                  const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream);
 
+/* Damping kernels of the kernel polynomial method. */
+enum { VBCSR_KPM_NONE = 0, VBCSR_KPM_JACKSON = 1 };
+
+/*
+ * vbcsr_kpm_dos -- density of states from Chebyshev moments (paper, section
+ * 5: the KPM with a damping kernel).  With M = n_moments and g_k = 1 (NONE)
+ * or the Jackson factors
+ *   g_k = [(M-k+1) cos(pi k/(M+1)) + sin(pi k/(M+1)) cot(pi/(M+1))] / (M+1),
+ *   rho[i] = [g_0 mu_0 + 2 sum_{k=1}^{M-1} g_k mu_k T_k(x_i)] / (pi sqrt(1 - x_i^2)),
+ * the series summed per point by Clenshaw's recurrence in FP64.  For the
+ * density per state, mu_k are the moments divided by (number of states x
+ * number of random vectors), e.g. averaged vbcsr_cheb_moments output / N.
+ *   mu    device, n_moments doubles (n_moments >= 1)
+ *   x     device, npts points of the scaled axis, |x| < 1 (|x| >= 1 gives
+ *         non-finite rho)
+ *   rho   device, npts doubles (must not overlap x)
+ *   work  device, n_moments doubles for the damped coefficients, or NULL
+ *         (allocated in the call; the call then synchronises `stream`)
+ * Asynchronous on `stream` when `work` is given.
+ * Errors: EINVAL, ENOMEM, EHIP.
+ */
+int vbcsr_kpm_dos(const double *mu, int32_t n_moments, int32_t damping, const double *x,
+                  int64_t npts, double *rho, double *work, void *stream);
+
+/*
+ * vbcsr_kpm_threshold -- the density threshold of the gap estimate (paper,
+ * section 5: a threshold tied to the KPM resolution): `fraction` of the peak
+ * height of one state of weight 1/n_states broadened by a Gaussian of the
+ * kernel width sigma = pi / n_moments (scaled axis),
+ *   threshold = fraction / (n_states * sigma * sqrt(2 pi)).
+ * Host only.  Errors: EINVAL.
+ */
+int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, double *threshold);
+
+/*
+ * vbcsr_kpm_gap -- the low-density interval: among runs of consecutive
+ * points with rho < threshold that have a point with rho >= threshold on both
+ * sides, the one whose bounding points are farthest apart; *lo and *hi
+ * receive those two bounding abscissae (NaN when there is no such run).
+ *   x, rho  host, npts values, x strictly ascending
+ * Host only.  Errors: EINVAL.
+ */
+int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double threshold, double *lo,
+                  double *hi);
+
 /* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
 void vbcsr_destroy(vbcsr_mat *A);
 

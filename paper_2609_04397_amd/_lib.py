@@ -24,6 +24,7 @@ CODE_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EDUP", -4: "ENOMEM", -5:
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PATH = {"auto": 0, "vec": 1, "mfma": 2}
 ORDER = {"auto": 0, "atom": 1, "rcm": 2}
+DAMPING = {"none": 0, "jackson": 1}
 
 # Every symbol declared in include/vbcsr.h, with (restype, argtypes).
 _p = ctypes.c_void_p
@@ -65,6 +66,9 @@ SIGNATURES = {
     "vbcsr_get_values": (_int, [_p, _p, _int, _p]),
     "vbcsr_spgemm": (_int, [ctypes.POINTER(_p), _p, _p, _f64, ctypes.POINTER(PlanOpts),
                             ctypes.POINTER(SpgemmStats), _p]),
+    "vbcsr_kpm_dos": (_int, [_p, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "vbcsr_kpm_threshold": (_int, [_i32, _i64, _f64, ctypes.POINTER(_f64)]),
+    "vbcsr_kpm_gap": (_int, [_p, _p, _i64, _f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
     "vbcsr_destroy": (None, [_p]),
     "vbcsr_last_error": (ctypes.c_char_p, []),
 }

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -903,6 +904,56 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (rc) return rc;
   st.ms_build = ms_since(t0);
   if (stats) *stats = st;
+  return VBCSR_OK;
+}
+
+int vbcsr_kpm_dos(const double *mu, int32_t n_moments, int32_t damping, const double *x,
+                  int64_t npts, double *rho, double *work, void *stream) {
+  if (n_moments < 1) return fail(VBCSR_EINVAL, "n_moments must be >= 1");
+  if (damping != VBCSR_KPM_NONE && damping != VBCSR_KPM_JACKSON)
+    return fail(VBCSR_EINVAL, "damping must be VBCSR_KPM_NONE or VBCSR_KPM_JACKSON");
+  if (npts < 0) return fail(VBCSR_EINVAL, "npts must be >= 0");
+  if (!mu || (npts > 0 && (!x || !rho))) return fail(VBCSR_EINVAL, "array pointer is NULL");
+  if (npts > 0 && ranges_overlap(x, sizeof(double) * npts, rho, sizeof(double) * npts))
+    return fail(VBCSR_EINVAL, "x and rho overlap");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *coef = work;
+  TempAllocs tmp;
+  int rc;
+  if (!coef && (rc = tmp.alloc(&coef, (size_t)n_moments))) return rc;
+  hipError_t e = launch_kpm_dos(mu, n_moments, damping, x, npts, coef, rho, s);
+  if (e != hipSuccess) return hip_fail(e, "kpm kernel launch");
+  // a workspace allocated here is freed on return: finish with it first
+  if (!work) HIP_TRY(hipStreamSynchronize(s), "kpm_dos");
+  return VBCSR_OK;
+}
+
+int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, double *threshold) {
+  if (n_moments < 1 || n_states < 1 || !(fraction > 0.0) || !threshold)
+    return fail(VBCSR_EINVAL, "need n_moments >= 1, n_states >= 1, fraction > 0, threshold");
+  const double sigma = M_PI / n_moments;
+  *threshold = fraction / ((double)n_states * sigma * std::sqrt(2.0 * M_PI));
+  return VBCSR_OK;
+}
+
+int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double threshold, double *lo,
+                  double *hi) {
+  if (!lo || !hi || (npts > 0 && (!x || !rho)) || npts < 0)
+    return fail(VBCSR_EINVAL, "array pointer is NULL or npts < 0");
+  for (int64_t i = 1; i < npts; ++i)
+    if (!(x[i] > x[i - 1])) return fail(VBCSR_EINVAL, "x must be strictly ascending");
+  *lo = *hi = std::nan("");
+  int64_t prev = -1;  // last point at or above the threshold
+  double best = -1.0;
+  for (int64_t i = 0; i < npts; ++i) {
+    if (!(rho[i] >= threshold)) continue;
+    if (prev >= 0 && i - prev > 1 && x[i] - x[prev] > best) {
+      best = x[i] - x[prev];
+      *lo = x[prev];
+      *hi = x[i];
+    }
+    prev = i;
+  }
   return VBCSR_OK;
 }
 

@@ -1469,6 +1469,53 @@ __global__ void __launch_bounds__(kThreads) k_unpack(const T *pages, const int64
   }
 }
 
+// ---------------------------------------------------------------------------
+// kernel polynomial method: damped coefficients and the density of states
+// ---------------------------------------------------------------------------
+// c_0 = g_0 mu_0, c_k = 2 g_k mu_k (k >= 1): the coefficients of the series
+// sum_k c_k T_k(x); g_k = 1 (no damping) or the Jackson factors
+// [(M-k+1) cos(q k) + sin(q k) cot(q)] / (M+1), q = pi / (M+1).
+__global__ void __launch_bounds__(kThreads) k_kpm_coef(const double *mu, int M, int damping,
+                                                       double *c) {
+  const int k = blockIdx.x * kThreads + threadIdx.x;
+  if (k >= M) return;
+  double g = 1.0;
+  if (damping == 1) {
+    const double q = M_PI / (M + 1);
+    g = ((double)(M - k + 1) * cos(q * k) + sin(q * k) * cos(q) / sin(q)) / (M + 1);
+  }
+  c[k] = (k == 0 ? 1.0 : 2.0) * g * mu[k];
+}
+
+// rho(x) = sum_k c_k T_k(x) / (pi sqrt(1 - x^2)) at every point, one lane per
+// point, the series summed by Clenshaw's recurrence from the highest degree
+// (b_k = c_k + 2x b_{k+1} - b_{k+2}; sum = c_0 + x b_1 - b_2).  All lanes read
+// the same c_k: the coefficients come through the scalar cache, 16 per
+// unrolled step.
+__global__ void __launch_bounds__(kThreads) k_kpm_dos(const double *c, int M, const double *x,
+                                                      int64_t np, double *rho) {
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const double xi = i < np ? x[i] : 0.0;
+  const double tx = 2.0 * xi;
+  double b1 = 0.0, b2 = 0.0;
+  int k = M - 1;
+  for (; k >= 16; k -= 16) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double b0 = fma(tx, b1, c[k - u] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+  }
+  for (; k >= 1; --k) {
+    const double b0 = fma(tx, b1, c[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  const double s = fma(xi, b1, c[0] - b2);
+  if (i < np) rho[i] = s / (M_PI * sqrt(1.0 - xi * xi));
+}
+
 }  // namespace
 
 int64_t product_workgroups(int64_t nrows) { return (nrows + kWaves - 1) / kWaves; }
@@ -1589,6 +1636,17 @@ hipError_t launch_unpack(const void *pages, int elem_bytes, const int64_t *pos,
     hipLaunchKernelGGL(k_unpack<float>, grid, dim3(kThreads), 0, s,
                        static_cast<const float *>(pages), pos, blk_row, col_idx, b, gbase, nnzb,
                        static_cast<float *>(dst));
+  return hipGetLastError();
+}
+
+hipError_t launch_kpm_dos(const double *mu, int M, int damping, const double *x, int64_t np,
+                          double *coef, double *rho, hipStream_t s) {
+  hipLaunchKernelGGL(k_kpm_coef, dim3((unsigned)((M + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, mu, M, damping, coef);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || np == 0) return e;
+  hipLaunchKernelGGL(k_kpm_dos, dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0,
+                     s, coef, M, x, np, rho);
   return hipGetLastError();
 }
 

@@ -136,4 +136,9 @@ hipError_t launch_unpack(const void *pages, int elem_bytes, const int64_t *pos,
                          const int32_t *blk_row, const int32_t *col_idx, const int32_t *b,
                          const int64_t *gbase, int64_t nnzb, void *dst, hipStream_t s);
 
+// Kernel polynomial method: coef[k] = damped, doubled moments (damping 0 =
+// none, 1 = Jackson), then rho[i] = density of states at x[i] (|x| < 1).
+hipError_t launch_kpm_dos(const double *mu, int M, int damping, const double *x, int64_t np,
+                          double *coef, double *rho, hipStream_t s);
+
 }  // namespace vbcsr
