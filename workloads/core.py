@@ -197,7 +197,7 @@ def random_cube(n_atoms: int, density: float, species, r_cut: float, decay: floa
     values = _symmetric_values(rng, b, row_ptr, col_idx, dist, decay)
     return Operator(name, b, row_ptr, col_idx, values, dist,
                     {"box": L, "r_cut": r_cut, "decay": decay, "seed": seed,
-                     "_rng": rng})
+                     "_rng": rng, "pos": pos})
 
 
 _SC_FIRST = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
