@@ -347,6 +347,87 @@ int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, do
 int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double threshold, double *lo,
                   double *hi);
 
+/* ---------------------------------------------------------------------------
+ * Reciprocal-space (k-sampled) operators.
+ * Paper, section 3.3, equation 4: a periodic real-space operator is a set of
+ * images O(R), one per integer lattice translation R, over the atoms of one
+ * cell; sampling a point k (fractional reciprocal coordinates) gives the
+ * complex block-sparse operator
+ *     O(k) = sum_R exp(-2 pi i k.R) O(R)                      (VBCSR_PHASE_R)
+ * or, in the alternative convention, block (i, j) of image R multiplied by
+ * exp(-2 pi i k.(R + tau_j - tau_i))                        (VBCSR_PHASE_R_TAU)
+ * with tau the atoms' fractional positions.  Blocks (i, j) of different
+ * images add into one block of O(k).  Complex vectors are interleaved
+ * (re, im) pairs: double for FP64 handles, float for FP32 handles; leading
+ * dimensions count complex elements.
+ * ------------------------------------------------------------------------- */
+typedef struct vbcsr_zmat vbcsr_zmat; /* opaque, owned by the library */
+enum { VBCSR_PHASE_R = 0, VBCSR_PHASE_R_TAU = 1 };
+
+/*
+ * vbcsr_zmat_create -- a periodic operator from its image blocks.
+ *   block_sizes, row_ptr, col_idx  as vbcsr_create, except that the same
+ *                (i, j) may appear once per image
+ *   image        host [nnzb], 0 <= image[t] < n_images: block t couples atom
+ *                i of the home cell to atom j of the cell shifted by
+ *                shifts[3*image[t] .. +3]
+ *   shifts       host [3*n_images] integer lattice translations
+ *   tau          host [3*n_atoms] fractional positions, or NULL (then only
+ *                VBCSR_PHASE_R can be sampled)
+ *   values       host, graph order, each real block row-major; NULL = zeros
+ *   prec         VBCSR_FP64 (complex double pages) or VBCSR_FP32 (complex
+ *                float pages); the image values are kept in FP64
+ *   opts         row_order is used (the pattern of O(k) is planned like
+ *                vbcsr_create's); may be NULL
+ * The pages of O(k) are zero until vbcsr_zmat_sample.  Synchronises stream.
+ * Errors: EINVAL, ESHAPE, EDUP (same (i, j) twice in one image),
+ * EUNSUPPORTED (BF16X3, or vbcsr_create's size limits on the pattern of
+ * O(k)), ENOMEM, EHIP.
+ */
+int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_sizes,
+                      const int64_t *row_ptr, const int32_t *col_idx, const int32_t *image,
+                      int32_t n_images, const int32_t *shifts, const double *tau,
+                      const double *values, int64_t n_values, vbcsr_prec prec,
+                      const vbcsr_plan_opts *opts, void *stream);
+
+/*
+ * vbcsr_zmat_sample -- assemble O(k) (and its conjugate transpose for the
+ * adjoint) on the device: one FP64 phase per image block, FP64 sums over the
+ * images of each block, stored in the handle's precision.
+ *   k           host [3], finite
+ *   convention  VBCSR_PHASE_R or VBCSR_PHASE_R_TAU (needs tau)
+ * Asynchronous on `stream`; products on other streams must not overlap it.
+ * Errors: EINVAL, EHIP.
+ */
+int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *stream);
+
+/*
+ * vbcsr_zmat_spmm -- Y <- alpha * op(O(k)) X + beta * Y, op = identity
+ * (adjoint = 0, section 3.2) or the conjugate transpose (adjoint = 1,
+ * equation 1: Y_j += O_ij^dagger X_i).  alpha, beta: host [2] (re, im);
+ * beta = 0 means Y is not read.  X, Y: device, N x nrhs complex, row-major.
+ * No atomics: every output row has one writer.
+ * Errors: EINVAL (null pointers, nrhs <= 0, ld < nrhs, overlap), EHIP.
+ */
+int vbcsr_zmat_spmm(const vbcsr_zmat *Z, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                    int32_t nrhs, const double *alpha, const double *beta, int32_t adjoint,
+                    void *stream);
+
+/* vbcsr_zmat_info -- N, blocks and values of O(k); any pointer may be NULL. */
+int vbcsr_zmat_info(const vbcsr_zmat *Z, int64_t *n_rows, int64_t *nnzb_k, int64_t *n_values_k);
+
+/* vbcsr_zmat_get_structure -- the pattern of O(k) (distinct (i, j), ascending
+ * j per row): row_ptr host [n_atoms+1], col_idx host [nnzb_k]. */
+int vbcsr_zmat_get_structure(const vbcsr_zmat *Z, int64_t *row_ptr, int32_t *col_idx);
+
+/* vbcsr_zmat_get_values -- the blocks of the last sampled O(k), graph order
+ * of that pattern, each block row-major, complex interleaved, written by a
+ * kernel on `stream` to `values` (device, n_values_k complex elements). */
+int vbcsr_zmat_get_values(const vbcsr_zmat *Z, void *values, void *stream);
+
+/* vbcsr_zmat_destroy -- free a handle (NULL is ignored); synchronises the device. */
+void vbcsr_zmat_destroy(vbcsr_zmat *Z);
+
 /* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
 void vbcsr_destroy(vbcsr_mat *A);
 

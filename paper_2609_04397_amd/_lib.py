@@ -25,6 +25,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PATH = {"auto": 0, "vec": 1, "mfma": 2}
 ORDER = {"auto": 0, "atom": 1, "rcm": 2}
 DAMPING = {"none": 0, "jackson": 1}
+PHASE = {"R": 0, "R+tau": 1}
 
 # Every symbol declared in include/vbcsr.h, with (restype, argtypes).
 _p = ctypes.c_void_p
@@ -69,6 +70,15 @@ SIGNATURES = {
     "vbcsr_kpm_dos": (_int, [_p, _i32, _i32, _p, _i64, _p, _p, _p]),
     "vbcsr_kpm_threshold": (_int, [_i32, _i64, _f64, ctypes.POINTER(_f64)]),
     "vbcsr_kpm_gap": (_int, [_p, _p, _i64, _f64, ctypes.POINTER(_f64), ctypes.POINTER(_f64)]),
+    "vbcsr_zmat_create": (_int, [ctypes.POINTER(_p), _i32, _p, _p, _p, _p, _i32, _p, _p, _p, _i64,
+                                 _int, ctypes.POINTER(PlanOpts), _p]),
+    "vbcsr_zmat_sample": (_int, [_p, _p, _i32, _p]),
+    "vbcsr_zmat_spmm": (_int, [_p, _p, _i64, _p, _i64, _i32, _p, _p, _i32, _p]),
+    "vbcsr_zmat_info": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                               ctypes.POINTER(_i64)]),
+    "vbcsr_zmat_get_structure": (_int, [_p, _p, _p]),
+    "vbcsr_zmat_get_values": (_int, [_p, _p, _p]),
+    "vbcsr_zmat_destroy": (None, [_p]),
     "vbcsr_destroy": (None, [_p]),
     "vbcsr_last_error": (ctypes.c_char_p, []),
 }

@@ -25,6 +25,14 @@ int fail(int code, const std::string &msg) {
   return code;
 }
 
+}  // namespace
+
+namespace vbcsr {
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+}  // namespace vbcsr
+
+namespace {
+
 int hip_fail(hipError_t e, const char *where) {
   return fail(VBCSR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }

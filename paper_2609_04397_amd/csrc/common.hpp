@@ -94,4 +94,8 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
                      const int32_t *bci, const int64_t *bpos, const double *bn, double eps,
                      SpgemmPlan &out);
 
+// Record `msg` as the calling thread's last error (read by vbcsr_last_error)
+// and return `code`.
+int set_error(int code, const std::string &msg);
+
 }  // namespace vbcsr

@@ -1,0 +1,216 @@
+// gfx950 kernels of the reciprocal-space operator O(k) = sum_R e^{-2 pi i k.R} O(R)
+// (paper, section 3.3, equation 4) and its complex products (section 3.2 and
+// equation 1 with the conjugate transpose).
+#include <hip/hip_runtime.h>
+
+#include "zkernels.hpp"
+
+namespace vbcsr {
+namespace {
+
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+
+template <typename T> struct C2;
+template <> struct C2<double> { using type = double2; };
+template <> struct C2<float> { using type = float2; };
+
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+}
+
+__global__ void __launch_bounds__(kThreads) k_zphase(ZPhaseParams P) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= P.nnzb) return;
+  const int32_t *R = P.shifts + 3 * (int64_t)P.image[t];
+  double d0 = R[0], d1 = R[1], d2 = R[2];
+  if (P.tau) {
+    const double *tj = P.tau + 3 * (int64_t)P.col_idx[t];
+    const double *ti = P.tau + 3 * (int64_t)P.blk_row[t];
+    d0 += tj[0] - ti[0];
+    d1 += tj[1] - ti[1];
+    d2 += tj[2] - ti[2];
+  }
+  const double th = -2.0 * M_PI * (P.k[0] * d0 + P.k[1] * d1 + P.k[2] * d2);
+  double sn, cs;
+  sincos(th, &sn, &cs);
+  P.ph[2 * t] = cs;
+  P.ph[2 * t + 1] = sn;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zsample(ZSampleParams P, T *fwd, T *tr) {
+  const int64_t kb = (int64_t)blockIdx.x * kWaves + wave_id();
+  if (kb >= P.nkb) return;
+  const int lane = threadIdx.x & 63;
+  const int bi = P.b[P.krow[kb]], bj = P.b[P.kcol[kb]];
+  const int64_t c0 = P.cptr[kb], c1 = P.cptr[kb + 1];
+  T *f = fwd + 2 * P.fwd_pos[kb];
+  T *g = tr + 2 * P.tr_pos[kb];
+  for (int e = lane; e < bi * bj; e += 64) {
+    double re = 0.0, im = 0.0;
+    for (int64_t c = c0; c < c1; ++c) {
+      const int64_t t = P.cblk[c];
+      const double v = P.values[P.gbase[t] + e];
+      re = fma(v, P.ph[2 * t], re);
+      im = fma(v, P.ph[2 * t + 1], im);
+    }
+    const int p = e / bj, q = e - p * bj;
+    const int64_t af = 2 * ((int64_t)q * bi + p);   // column-major in the forward panel
+    const int64_t at = 2 * (int64_t)e;              // row-major (= A^H column-major)
+    f[af] = (T)re;
+    f[af + 1] = (T)im;
+    g[at] = (T)re;
+    g[at + 1] = (T)(-im);
+  }
+}
+
+// One wave per panel (block row of op(O)): lane (g, p) takes panel row p and
+// the panel columns k = g, g + G, ... (G = floor(64 / b) groups), NR
+// right-hand sides per pass; groups are reduced by shuffles.  Every complex
+// product is four FMAs in T.
+template <typename T, int NR>
+__global__ void __launch_bounds__(kThreads) k_zspmm(ZSpmmParams<T> P) {
+  using V = typename C2<T>::type;
+  const int row = blockIdx.x * kWaves + wave_id();
+  if (row >= P.nrows) return;
+  const int lane = threadIdx.x & 63;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  const int G = 64 / b;
+  const int g = lane / b, p = lane - g * b;
+  const bool act = g < G;
+  const V *__restrict__ A = reinterpret_cast<const V *>(P.pages) + rd.vbase;
+  const int32_t *__restrict__ cx = P.colx + rd.cbase;
+  const V *__restrict__ X = reinterpret_cast<const V *>(P.X);
+  V *__restrict__ Y = reinterpret_cast<V *>(P.Y);
+  for (int c0 = 0; c0 < P.nrhs; c0 += NR) {
+    T re[NR], im[NR];
+#pragma unroll
+    for (int c = 0; c < NR; ++c) re[c] = im[c] = T(0);
+    if (act) {
+      for (int k = g; k < K; k += G) {
+        const V a = A[(int64_t)k * b + p];
+        const V *xr = X + (int64_t)cx[k] * P.ldx + c0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) {
+          if (c0 + c < P.nrhs) {
+            const V x = xr[c];
+            re[c] = fma(a.x, x.x, re[c]);
+            re[c] = fma(-a.y, x.y, re[c]);
+            im[c] = fma(a.x, x.y, im[c]);
+            im[c] = fma(a.y, x.x, im[c]);
+          }
+        }
+      }
+    }
+    for (int st = 1; st < G; st <<= 1) {
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        const T orr = __shfl_down(re[c], st * b, 64);
+        const T oi = __shfl_down(im[c], st * b, 64);
+        if (act && (g & (2 * st - 1)) == 0 && g + st < G) {
+          re[c] += orr;
+          im[c] += oi;
+        }
+      }
+    }
+    if (lane < b) {
+      V *yr = Y + (int64_t)(rd.yrow + p) * P.ldy + c0;
+#pragma unroll
+      for (int c = 0; c < NR; ++c) {
+        if (c0 + c < P.nrhs) {
+          const double sr = re[c], si = im[c];
+          double yr_ = P.ar * sr - P.ai * si, yi_ = P.ar * si + P.ai * sr;
+          if (P.br != 0.0 || P.bi != 0.0) {
+            const V y = yr[c];
+            yr_ += P.br * (double)y.x - P.bi * (double)y.y;
+            yi_ += P.br * (double)y.y + P.bi * (double)y.x;
+          }
+          V o;
+          o.x = (T)yr_;
+          o.y = (T)yi_;
+          yr[c] = o;
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zunpack(const T *fwd, const int64_t *pos,
+                                                      const int32_t *krow, const int32_t *kcol,
+                                                      const int32_t *b, const int64_t *kbase,
+                                                      int64_t nkb, T *dst) {
+  const int64_t kb = (int64_t)blockIdx.x * kWaves + wave_id();
+  if (kb >= nkb) return;
+  const int lane = threadIdx.x & 63;
+  const int bi = b[krow[kb]], bj = b[kcol[kb]];
+  const T *f = fwd + 2 * pos[kb];
+  T *d = dst + 2 * kbase[kb];
+  for (int e = lane; e < bi * bj; e += 64) {
+    const int p = e / bj, q = e - p * bj;
+    d[2 * e] = f[2 * ((int64_t)q * bi + p)];
+    d[2 * e + 1] = f[2 * ((int64_t)q * bi + p) + 1];
+  }
+}
+
+template <typename T>
+hipError_t launch_zspmm_t(const ZSpmmParams<T> &p, hipStream_t s) {
+  if (p.nrows == 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.nrows + kWaves - 1) / kWaves));
+  if (p.nrhs == 1)
+    hipLaunchKernelGGL((k_zspmm<T, 1>), grid, dim3(kThreads), 0, s, p);
+  else if (p.nrhs == 2)
+    hipLaunchKernelGGL((k_zspmm<T, 2>), grid, dim3(kThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_zspmm<T, 4>), grid, dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_zphase(const ZPhaseParams &p, hipStream_t s) {
+  if (p.nnzb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zphase, dim3((unsigned)((p.nnzb + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_zsample(const ZSampleParams &p, void *fwd, void *tr, int elem_bytes,
+                          hipStream_t s) {
+  if (p.nkb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((p.nkb + kWaves - 1) / kWaves));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_zsample<double>, grid, dim3(kThreads), 0, s, p,
+                       static_cast<double *>(fwd), static_cast<double *>(tr));
+  else
+    hipLaunchKernelGGL(k_zsample<float>, grid, dim3(kThreads), 0, s, p,
+                       static_cast<float *>(fwd), static_cast<float *>(tr));
+  return hipGetLastError();
+}
+
+hipError_t launch_zspmm_f64(const ZSpmmParams<double> &p, hipStream_t s) {
+  return launch_zspmm_t(p, s);
+}
+hipError_t launch_zspmm_f32(const ZSpmmParams<float> &p, hipStream_t s) {
+  return launch_zspmm_t(p, s);
+}
+
+hipError_t launch_zunpack(const void *fwd, int elem_bytes, const int64_t *pos,
+                          const int32_t *krow, const int32_t *kcol, const int32_t *b,
+                          const int64_t *kbase, int64_t nkb, void *dst, hipStream_t s) {
+  if (nkb == 0) return hipSuccess;
+  const dim3 grid((unsigned)((nkb + kWaves - 1) / kWaves));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_zunpack<double>, grid, dim3(kThreads), 0, s,
+                       static_cast<const double *>(fwd), pos, krow, kcol, b, kbase, nkb,
+                       static_cast<double *>(dst));
+  else
+    hipLaunchKernelGGL(k_zunpack<float>, grid, dim3(kThreads), 0, s,
+                       static_cast<const float *>(fwd), pos, krow, kcol, b, kbase, nkb,
+                       static_cast<float *>(dst));
+  return hipGetLastError();
+}
+
+}  // namespace vbcsr
