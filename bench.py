@@ -78,6 +78,8 @@ def parse():
                     help="only run the block product records (G1, A A) and print them")
     ap.add_argument("--kpm", action="store_true",
                     help="only run the KPM density-of-states records and print them")
+    ap.add_argument("--kspace", action="store_true",
+                    help="only run the reciprocal-space operator records and print them")
     return ap.parse_args()
 
 
@@ -86,9 +88,10 @@ def main():
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
-    if args.spgemm or args.kpm:
+    if args.spgemm or args.kpm or args.kspace:
         recs = (spgemm_records(with_cpu=not args.no_cpu) if args.spgemm else []) + \
-            (kpm_records(with_cpu=not args.no_cpu) if args.kpm else [])
+            (kpm_records(with_cpu=not args.no_cpu) if args.kpm else []) + \
+            (kspace_records() if args.kspace else [])
         for rec in recs:
             print(json.dumps(rec), flush=True)
         return
@@ -390,7 +393,47 @@ def run_sweep(path):
         emit(rec)
     for rec in kpm_records(with_cpu=True):
         emit(rec)
+    for rec in kspace_records():
+        emit(rec)
     out.close()
+
+
+def kspace_records():
+    """Reciprocal-space form of the 100k-atom cube (C5 as a periodic cell:
+    every block carries its minimum-image shift, 27 images): sampling O(k)
+    (R+tau convention) and complex products with O(k) and O(k)^H, FP64.
+    Algorithmic bytes: sampling reads the real values (8 B each) and writes
+    both complex pages (2 x 16 B per value); a product reads the complex
+    pages once (16 B per value), 4 B per panel column index, X once and
+    writes Y (16 B per complex element)."""
+    import torch
+    from paper_2609_04397_amd.kspace import KMatrix
+    from workloads.configs import make_operator
+    from workloads.periodic import from_cube
+
+    Z = from_cube(make_operator("C5"))
+    KM = KMatrix.from_images(Z)
+    size = {"workload": "C5 periodic", "n_atoms": Z.n, "N": Z.N, "nnzb": Z.nnzb,
+            "n_values": Z.nnz, "n_images": int(Z.shifts.shape[0])}
+    k = np.array([0.2, -0.1, 0.35])
+    ms = _time_call(lambda: KM.sample(k, "R+tau"))
+    nb = 8 * Z.nnz + 2 * 16 * KM.n_values_k
+    recs = [dict(size, op="kspace sample", prec="fp64", nrhs=None, ms=round(ms, 4),
+                 gbs=round(nb / ms / 1e6, 1), hbm_frac=round(nb / ms / 1e6 / HBM_PEAK_GBS, 4),
+                 alg_bytes=int(nb))]
+    dev = torch.device("cuda", 0)
+    cols = int(sum(int(Z.b[j]) for j in KM.structure()[1]))
+    for nrhs in (1, 4, 16):
+        X = torch.randn(Z.N, nrhs, dtype=torch.complex128, device=dev)
+        Y = torch.empty_like(X)
+        for adj in (False, True):
+            ms = _time_call(lambda: KM.spmm(X, Y, adjoint=adj))
+            nb = 16 * KM.n_values_k + 4 * cols + 2 * 16 * Z.N * nrhs
+            recs.append(dict(size, op="kspace spmm_h" if adj else "kspace spmm", prec="fp64",
+                             nrhs=nrhs, ms=round(ms, 4), gbs=round(nb / ms / 1e6, 1),
+                             hbm_frac=round(nb / ms / 1e6 / HBM_PEAK_GBS, 4), alg_bytes=int(nb)))
+    KM.close()
+    return recs
 
 
 def kpm_records(with_cpu=True):

@@ -88,20 +88,35 @@ __global__ void __launch_bounds__(kThreads) k_zspmm(ZSpmmParams<T> P) {
     T re[NR], im[NR];
 #pragma unroll
     for (int c = 0; c < NR; ++c) re[c] = im[c] = T(0);
-    if (act) {
+    if (act && g < K) {
+      // the operands of column k + G are in flight while column k
+      // multiplies; the index is clamped to the last column (no branch
+      // around the loads), the clamped copy is never multiplied
+      const int nc = min(NR, P.nrhs - c0);
+      V a = A[(int64_t)g * b + p];
+      V x[NR];
+      {
+        const V *xr = X + (int64_t)cx[g] * P.ldx + c0;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) x[c] = xr[min(c, nc - 1)];
+      }
       for (int k = g; k < K; k += G) {
-        const V a = A[(int64_t)k * b + p];
-        const V *xr = X + (int64_t)cx[k] * P.ldx + c0;
+        const int kn = min(k + G, K - 1);
+        const V an = A[(int64_t)kn * b + p];
+        const V *xn = X + (int64_t)cx[kn] * P.ldx + c0;
+        V xv[NR];
+#pragma unroll
+        for (int c = 0; c < NR; ++c) xv[c] = xn[min(c, nc - 1)];
 #pragma unroll
         for (int c = 0; c < NR; ++c) {
-          if (c0 + c < P.nrhs) {
-            const V x = xr[c];
-            re[c] = fma(a.x, x.x, re[c]);
-            re[c] = fma(-a.y, x.y, re[c]);
-            im[c] = fma(a.x, x.y, im[c]);
-            im[c] = fma(a.y, x.x, im[c]);
-          }
+          re[c] = fma(a.x, x[c].x, re[c]);
+          re[c] = fma(-a.y, x[c].y, re[c]);
+          im[c] = fma(a.x, x[c].y, im[c]);
+          im[c] = fma(a.y, x[c].x, im[c]);
         }
+        a = an;
+#pragma unroll
+        for (int c = 0; c < NR; ++c) x[c] = xv[c];
       }
     }
     for (int st = 1; st < G; st <<= 1) {
@@ -159,12 +174,17 @@ template <typename T>
 hipError_t launch_zspmm_t(const ZSpmmParams<T> &p, hipStream_t s) {
   if (p.nrows == 0) return hipSuccess;
   const dim3 grid((unsigned)((p.nrows + kWaves - 1) / kWaves));
+  // right-hand sides per pass: every pass streams the pages once more
   if (p.nrhs == 1)
     hipLaunchKernelGGL((k_zspmm<T, 1>), grid, dim3(kThreads), 0, s, p);
   else if (p.nrhs == 2)
     hipLaunchKernelGGL((k_zspmm<T, 2>), grid, dim3(kThreads), 0, s, p);
-  else
+  else if (p.nrhs <= 4)
     hipLaunchKernelGGL((k_zspmm<T, 4>), grid, dim3(kThreads), 0, s, p);
+  else if (p.nrhs <= 8)
+    hipLaunchKernelGGL((k_zspmm<T, 8>), grid, dim3(kThreads), 0, s, p);
+  else
+    hipLaunchKernelGGL((k_zspmm<T, 16>), grid, dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
 
