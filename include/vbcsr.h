@@ -381,8 +381,8 @@ enum { VBCSR_PHASE_R = 0, VBCSR_PHASE_R_TAU = 1 };
  *                vbcsr_create's); may be NULL
  * The pages of O(k) are zero until vbcsr_zmat_sample.  Synchronises stream.
  * Errors: EINVAL, ESHAPE, EDUP (same (i, j) twice in one image),
- * EUNSUPPORTED (BF16X3, or vbcsr_create's size limits on the pattern of
- * O(k)), ENOMEM, EHIP.
+ * EUNSUPPORTED (BF16X3, vbcsr_create's size limits on the pattern of O(k),
+ * or a block row or column of O(k) with 2^27 or more values), ENOMEM, EHIP.
  */
 int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_sizes,
                       const int64_t *row_ptr, const int32_t *col_idx, const int32_t *image,
@@ -406,7 +406,9 @@ int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *
  * (adjoint = 0, section 3.2) or the conjugate transpose (adjoint = 1,
  * equation 1: Y_j += O_ij^dagger X_i).  alpha, beta: host [2] (re, im);
  * beta = 0 means Y is not read.  X, Y: device, N x nrhs complex, row-major.
- * No atomics: every output row has one writer.
+ * No atomics: every output row has one writer.  FP64 with nrhs >= 16 (and X
+ * spanning less than 2^31 bytes) runs on matrix cores, otherwise on vector
+ * FMA.
  * Errors: EINVAL (null pointers, nrhs <= 0, ld < nrhs, overlap), EHIP.
  */
 int vbcsr_zmat_spmm(const vbcsr_zmat *Z, const void *X, int64_t ldx, void *Y, int64_t ldy,

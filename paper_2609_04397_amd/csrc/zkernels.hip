@@ -152,6 +152,100 @@ __global__ void __launch_bounds__(kThreads) k_zspmm(ZSpmmParams<T> P) {
   }
 }
 
+// Complex product on FP64 matrix cores, for 16 right-hand sides per tile:
+// one wave per panel, M = panel rows in tiles of 16, K = panel columns in
+// slices of 4, N = 16 right-hand sides per tile, NT tiles per pass.  Lane
+// (m, kq) loads 16 bytes of A (row m, column 4s + kq: one complex value) and,
+// per tile, 16 bytes of X (row colx[4s + kq], right-hand side m); four real
+// products per complex tile accumulate Ar Xr, Ai Xi, Ar Xi, Ai Xr.  Rows past
+// the panel, columns past K and right-hand sides past nrhs read zeros
+// through the buffer bounds.  The next slice's operands are in flight while
+// the current one multiplies.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t zrsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+__device__ __forceinline__ double2 zload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kThreads) k_zspmm_mfma(ZSpmmParams<double> P, uint32_t xbytes) {
+  const int row = blockIdx.x * kWaves + wave_id();
+  if (row >= P.nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  constexpr uint32_t kOut = 0x80000000u;
+  const __amdgpu_buffer_rsrc_t ra = zrsrc(reinterpret_cast<const double2 *>(P.pages) + rd.vbase,
+                                          (uint32_t)K * (uint32_t)b * 16u);
+  const __amdgpu_buffer_rsrc_t rx = zrsrc(P.X, xbytes);
+  const int32_t *__restrict__ cx = P.colx + rd.cbase;
+  const int nsl = (K + 3) >> 2;
+  double2 *__restrict__ Y = reinterpret_cast<double2 *>(P.Y);
+  for (int mt = 0; mt * 16 < b; ++mt) {
+    const int ar = mt * 16 + m;
+    for (int c0 = 0; c0 < P.nrhs; c0 += 16 * NT) {
+      v4d rr[NT], ii[NT], ri[NT], ir[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) rr[t] = ii[t] = ri[t] = ir[t] = v4d{0.0, 0.0, 0.0, 0.0};
+      auto ld = [&](int s, double2 &a, double2 (&x)[NT]) {
+        const int k = 4 * s + kq;
+        a = zload(ra, ar < b ? (uint32_t)(k * b + ar) * 16u : kOut);
+        const int xr = k < K ? cx[min(k, K - 1)] : -1;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const int c = c0 + t * 16 + m;
+          x[t] = zload(rx, xr >= 0 && c < P.nrhs
+                                ? (uint32_t)(((int64_t)xr * P.ldx + c) * 16)
+                                : kOut);
+        }
+      };
+      if (nsl > 0) {
+        double2 a, x[NT];
+        ld(0, a, x);
+        for (int s = 0; s < nsl; ++s) {
+          double2 an, xn[NT];
+          ld(min(s + 1, nsl - 1), an, xn);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            rr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, x[t].x, rr[t], 0, 0, 0);
+            ii[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, x[t].y, ii[t], 0, 0, 0);
+            ri[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, x[t].y, ri[t], 0, 0, 0);
+            ir[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, x[t].x, ir[t], 0, 0, 0);
+          }
+          a = an;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) x[t] = xn[t];
+        }
+      }
+      // accumulator element e of quarter-wave kq: tile row kq + 4e, column m
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int c = c0 + t * 16 + m;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = mt * 16 + kq + 4 * e;
+          if (r < b && c < P.nrhs) {
+            const double sr = rr[t][e] - ii[t][e], si = ri[t][e] + ir[t][e];
+            double2 *yp = Y + (int64_t)(rd.yrow + r) * P.ldy + c;
+            double yr = P.ar * sr - P.ai * si, yi = P.ar * si + P.ai * sr;
+            if (P.br != 0.0 || P.bi != 0.0) {
+              const double2 y = *yp;
+              yr += P.br * y.x - P.bi * y.y;
+              yi += P.br * y.y + P.bi * y.x;
+            }
+            *yp = double2{yr, yi};
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_zunpack(const T *fwd, const int64_t *pos,
                                                       const int32_t *krow, const int32_t *kcol,
@@ -211,7 +305,19 @@ hipError_t launch_zsample(const ZSampleParams &p, void *fwd, void *tr, int elem_
 }
 
 hipError_t launch_zspmm_f64(const ZSpmmParams<double> &p, hipStream_t s) {
-  return launch_zspmm_t(p, s);
+  // 16 or more right-hand sides go to matrix cores when X spans less than
+  // 2^31 bytes (one buffer descriptor with 32-bit offsets)
+  const int64_t xspan = ((int64_t)p.xrows - 1) * p.ldx + p.nrhs;
+  if (p.nrhs < 16 || p.nrows == 0 || xspan * 16 >= (int64_t(1) << 31)) return launch_zspmm_t(p, s);
+  const dim3 grid((unsigned)((p.nrows + kWaves - 1) / kWaves));
+  const uint32_t xb = (uint32_t)(xspan * 16);
+  if (p.nrhs <= 16)
+    hipLaunchKernelGGL(k_zspmm_mfma<1>, grid, dim3(kThreads), 0, s, p, xb);
+  else if (p.nrhs <= 32)
+    hipLaunchKernelGGL(k_zspmm_mfma<2>, grid, dim3(kThreads), 0, s, p, xb);
+  else
+    hipLaunchKernelGGL(k_zspmm_mfma<4>, grid, dim3(kThreads), 0, s, p, xb);
+  return hipGetLastError();
 }
 hipError_t launch_zspmm_f32(const ZSpmmParams<float> &p, hipStream_t s) {
   return launch_zspmm_t(p, s);

@@ -52,6 +52,7 @@ struct ZSpmmParams {
   int64_t ldy;
   int32_t nrhs;
   double ar, ai, br, bi;
+  int64_t xrows;  // rows of X (columns of the operator)
 };
 
 hipError_t launch_zphase(const ZPhaseParams &p, hipStream_t s);

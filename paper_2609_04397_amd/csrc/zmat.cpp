@@ -160,6 +160,24 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
   nkv = kbase[nkb];
   int rc = validate_graph(n_atoms, block_sizes, krp.data(), kci.data(), nkv, err);
   if (rc) return zfail(rc, err);
+  {
+    // complex pages take 16 bytes per value: a block row or block column is
+    // addressed with 32-bit byte offsets, so it must hold fewer than 2^27
+    std::vector<int64_t> colv(n_atoms, 0);
+    for (int32_t i = 0; i < n_atoms; ++i) {
+      int64_t rv = 0;
+      for (int64_t c = krp[i]; c < krp[i + 1]; ++c) {
+        const int64_t v = (int64_t)block_sizes[i] * block_sizes[kci[c]];
+        rv += v;
+        colv[kci[c]] += v;
+      }
+      if (rv >= (int64_t(1) << 27))
+        return zfail(VBCSR_EUNSUPPORTED, "block row " + std::to_string(i) + " of O(k) holds 2^27 or more values");
+    }
+    for (int32_t j = 0; j < n_atoms; ++j)
+      if (colv[j] >= (int64_t(1) << 27))
+        return zfail(VBCSR_EUNSUPPORTED, "block column " + std::to_string(j) + " of O(k) holds 2^27 or more values");
+  }
   HostPlan plan;
   build_plan(n_atoms, block_sizes, krp.data(), kci.data(), opts ? opts->row_order : 0, plan);
   // contributions of every k-space block, in graph order
@@ -286,12 +304,12 @@ int vbcsr_zmat_spmm(const vbcsr_zmat *Z, const void *X, int64_t ldx, void *Y, in
   if (Z->prec == VBCSR_FP64) {
     ZSpmmParams<double> p{Z->rows[d], Z->n, Z->colx[d], static_cast<const double *>(Z->pages[d]),
                           static_cast<const double *>(X), ldx, static_cast<double *>(Y), ldy, nrhs,
-                          alpha[0], alpha[1], beta[0], beta[1]};
+                          alpha[0], alpha[1], beta[0], beta[1], Z->N};
     e = launch_zspmm_f64(p, s);
   } else {
     ZSpmmParams<float> p{Z->rows[d], Z->n, Z->colx[d], static_cast<const float *>(Z->pages[d]),
                          static_cast<const float *>(X), ldx, static_cast<float *>(Y), ldy, nrhs,
-                         alpha[0], alpha[1], beta[0], beta[1]};
+                         alpha[0], alpha[1], beta[0], beta[1], Z->N};
     e = launch_zspmm_f32(p, s);
   }
   if (e != hipSuccess) return zhip(e, "complex product kernel launch");

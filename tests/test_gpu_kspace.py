@@ -61,7 +61,7 @@ def test_sample_and_products(conv, seed, herm, prec):
                 tol = (1e-15 if prec == "fp64" else 1e-6) * max(1.0, np.abs(blk).max()) * 8
                 assert np.abs(vals[pos:pos + sz] - blk).max() <= tol
                 pos += sz
-        for nrhs in (1, 2, 3, 8, 16, 21):
+        for nrhs in (1, 2, 3, 8, 16, 21, 40):
             X = rng.standard_normal((Z.N, nrhs)) + 1j * rng.standard_normal((Z.N, nrhs))
             check_products(Z, K, KM, X, prec)
         Y0 = rng.standard_normal((Z.N, 5)) + 1j * rng.standard_normal((Z.N, 5))
