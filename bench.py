@@ -232,6 +232,7 @@ def main():
         "fwd_bwd_over_fwd": round(sum(r["avg_ms"] for r in fb) / fwd[0]["avg_ms"], 3)
         if len(fb) == 3 else None,
         "setup_s": {"generate": round(gen_s, 2), "create_4_handles": round(create_s, 2)},
+        "device": device_info(),
     }
     if args.calib:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -250,6 +251,34 @@ def main():
     if not args.no_cpu and len(kernels) == 7:
         out["cpu_baseline"] = cpu_baseline(op, opc, X1, X32, G32, R64, total_bytes)
     print(json.dumps(out))
+
+
+def device_info():
+    """What the runtime and rocminfo report for GPU 0 (compute units, clock,
+    memory), beside the datasheet figures the roofline uses (256 CUs at up to
+    2.4 GHz, 288 GB HBM3E at 8 TB/s)."""
+    import subprocess
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    info = {"name": p.name, "arch": getattr(p, "gcnArchName", None),
+            "compute_units": p.multi_processor_count,
+            "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+    try:
+        txt = subprocess.run(["rocminfo"], capture_output=True, text=True, timeout=30).stdout
+        for agent in txt.split("Agent ")[1:]:
+            if "gfx" in agent and "Compute Unit" in agent:
+                for line in agent.splitlines():
+                    line = line.strip()
+                    if line.startswith("Max Clock Freq. (MHz):"):
+                        info["rocminfo_max_clock_mhz"] = int(line.split(":")[1].split()[0])
+                    elif line.startswith("Compute Unit:"):
+                        info["rocminfo_compute_units"] = int(line.split(":")[1].split()[0])
+                    elif line.startswith("Marketing Name:"):
+                        info["rocminfo_name"] = line.split(":", 1)[1].strip()
+                break
+    except Exception as e:  # rocminfo missing or slow: report what the runtime gave
+        info["rocminfo_error"] = str(e)[:80]
+    return info
 
 
 def _time_call(fn, warm=3, reps=7):
@@ -329,7 +358,11 @@ def run_sweep(path):
     plan = [("C1", [("fp64", (1, 2, 4, 8, 16), True)]),
             ("C2", [("fp64", (1, 2, 4, 8, 16, 32, 64), True), ("fp32", (1, 8, 64), False),
                     ("bf16x3", (64,), False)]),
-            ("C3", [("fp64", (1, 2, 4, 8, 64), True)])]
+            ("C3", [("fp64", (1, 2, 4, 8, 64), True)]),
+            # the paper's fixed-block (b = 8) and variable-block (b in 9..20)
+            # kernel-efficiency domains, ~500 MiB each, SpMV and nrhs 16
+            ("P8", [("fp64", (1, 16), True)]),
+            ("G1", [("fp64", (1, 16), True)])]
     for name, forms in plan:
         op, _ = make_config(name, nrhs=1)
         size = {"workload": name, "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz}
@@ -342,7 +375,7 @@ def run_sweep(path):
                 ms = _time_call(lambda: A.spmm(X, Y))
                 emit(dict(size, op="spmm", prec=prec, nrhs=nrhs, **rate(op, prec, nrhs, ms),
                           cache_resident=bool(op.nnz * (8 if prec == "fp64" else 4) < 256e6)))
-                if with_t and nrhs in (1, 8, 32, 64):
+                if with_t and nrhs in (1, 8, 16, 32, 64):
                     ms = _time_call(lambda: A.spmm_t(X, Y))
                     emit(dict(size, op="spmm_t", prec=prec, nrhs=nrhs, **rate(op, prec, nrhs, ms),
                               cache_resident=bool(op.nnz * 8 < 256e6)))

@@ -199,3 +199,20 @@ def test_c3_zincblende_sampled():
         print("C3 nrhs %d rel_F %.2e" % (nrhs, r))
     check_adjoint_rows(op, A, np.ascontiguousarray(X[:, :8]), "fp64", atoms, srows, "C3 adjoint 8")
     A.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("name", ["P8", "G1"])
+def test_paper_shaped_domains_sampled(name):
+    """The paper's fixed-block (b = 8) and variable-block (b in 9..20)
+    domains at about 500 MiB of FP64 values, SpMV and SpMM with 16
+    right-hand sides (the kernel-efficiency shapes), sampled rows."""
+    op, vec = make_config(name, nrhs=16)
+    X = vec["X"]
+    atoms, srows = sample_atoms(op, 600, 3)
+    A = Matrix.from_operator(op)
+    for nrhs in (1, 16):
+        print("case", name, "nrhs", nrhs, flush=True)
+        Xn = np.ascontiguousarray(X[:, :nrhs])
+        check_forward_rows(op, A, Xn, "fp64", atoms, srows, "%s fwd %d" % (name, nrhs))
+    check_adjoint_rows(op, A, np.ascontiguousarray(X), "fp64", atoms, srows, "%s adjoint" % name)

@@ -17,6 +17,8 @@ not public, so these seeded stand-ins replace them:
   5 A, values as C1 rounded to FP32, nrhs 32, X and G drawn N(0,1).
 * ``FD50`` 50 atoms in a 10 A periodic cube, b in {1, 4, 9} (10/20/20),
   cutoff 5 A, nrhs 32: the finite-difference instance.
+* ``P8``  the paper's fixed-block (BSR) domain: 38,400 atoms, density 0.05,
+  every b = 8, cutoff 5 A, values as C1 (about 510 MiB of FP64 values).
 * ``G1``  the block-product (SpGEMM) operand: 11,520 atoms, density 0.05,
   b uniform over 9..20 (960 atoms each, the paper's variable-block range),
   cutoff 5 A, values as C1 (about 500 MiB of FP64 values, the storage the
@@ -32,8 +34,8 @@ import numpy as np
 from .core import (random_cube, sc_lattice, zincblende_sphere, multivector,
                    inf_norm_scale, scaled)
 
-CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5", "FD50", "G1")
-DEFAULT_NRHS = {"C1": 16, "C2": 32, "C3": 64, "C4": 64, "C5": 32, "FD50": 32, "G1": 16}
+CONFIG_NAMES = ("C1", "C2", "C3", "C4", "C5", "FD50", "G1", "P8")
+DEFAULT_NRHS = {"C1": 16, "C2": 32, "C3": 64, "C4": 64, "C5": 32, "FD50": 32, "G1": 16, "P8": 16}
 
 
 def _round_counts(total, fracs):
@@ -62,6 +64,9 @@ def make_operator(name: str, scale: float = 1.0):
         # 50 atoms in a 10 A box: density 0.05
         return random_cube(50, 0.05, [(1, 10), (4, 20), (9, 20)], 5.0, 2.0,
                            seed=55, name="FD50", box=10.0)
+    if name == "P8":
+        n = max(60, int(round(38_400 * scale)))
+        return random_cube(n, 0.05, [(8, n)], 5.0, 2.0, seed=8, name="P8")
     if name == "G1":
         n = max(60, int(round(11_520 * scale)) // 12 * 12)
         return random_cube(n, 0.05, [(bb, n // 12) for bb in range(9, 21)], 5.0, 2.0,
