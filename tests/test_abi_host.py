@@ -279,3 +279,44 @@ def test_c3_shape_classes_full_size_small():
     rc, ns, shapes, _ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz)
     assert rc == 0 and ns == 9
     assert {(int(a), int(c)) for a, c, _ in shapes} == {(x, y) for x in (1, 9, 13) for y in (1, 9, 13)}
+
+
+def test_large_graph_threaded_planner(lib):
+    """A graph above the planner's threading threshold (12,000 atoms): page
+    maps tile the pages, rows are grouped by (b_j, j), columns by (b_i, i),
+    shape classes recount, and of two bad rows the first one is reported."""
+    from workloads.configs import make_operator
+    op = make_operator("C5", 0.12)
+    assert op.n >= 8192
+    fwd = np.zeros(op.nnzb, np.int64)
+    tr = np.zeros(op.nnzb, np.int64)
+    for order in ("atom", "rcm"):
+        rc, ns, shapes, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd, tr, order=order)
+        assert rc == 0
+        sizes = op.block_sizes
+        for pos in (fwd, tr):
+            o = np.argsort(pos)
+            gaps = pos[o][1:] - (pos[o] + sizes[o])[:-1]
+            assert pos[o][0] == 0 and np.all((gaps >= 0) & (gaps < 4))
+    rows = op.block_rows
+    key = np.lexsort((op.col_idx, op.b[op.col_idx], rows))
+    rc, *_ = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd, tr, order="atom")
+    assert np.all(np.diff(fwd[key]) > 0)
+    keyt = np.lexsort((rows, op.b[rows], op.col_idx))
+    assert np.all(np.diff(tr[keyt]) > 0)
+    u, c = np.unique(np.stack([op.b[rows], op.b[op.col_idx]], 1), axis=0, return_counts=True)
+    rc, ns, shapes, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz)
+    assert np.array_equal(shapes[:, :2], u) and np.array_equal(shapes[:, 2], c)
+    # two bad rows far apart: a duplicate in a late row, an out-of-range
+    # column in an earlier one; the earlier row is reported
+    ci = op.col_idx.copy()
+    late, early = op.n - 5, 7000
+    s_late = int(op.row_ptr[late])
+    ci[s_late + 1] = ci[s_late]
+    rc = _case(lib, op.b, op.row_ptr, ci, op.nnz)
+    assert rc == _lib.VBCSR_EDUP
+    assert "duplicate block (%d," % late in lib.vbcsr_last_error().decode()
+    ci[int(op.row_ptr[early])] = op.n + 3
+    rc = _case(lib, op.b, op.row_ptr, ci, op.nnz)
+    assert rc == _lib.VBCSR_EINVAL
+    assert ("in row %d" % early) in lib.vbcsr_last_error().decode()
