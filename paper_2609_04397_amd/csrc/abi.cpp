@@ -261,13 +261,15 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
 }
 
 int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                 int64_t n_values, const vbcsr_plan_opts *opts, HostPlan &plan) {
+                 int64_t n_values, const vbcsr_plan_opts *opts, HostPlan &plan,
+                 bool with_columns) {
   std::string err;
   if (opts && (opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
     return fail(VBCSR_EINVAL, "row_order must be one of VBCSR_ORDER_*");
   int rc = validate_graph(n, b, row_ptr, col_idx, n_values, err);
   if (rc) return fail(rc, err);
-  build_plan(n, b, row_ptr, col_idx, opts ? opts->row_order : VBCSR_ORDER_AUTO, plan);
+  build_plan(n, b, row_ptr, col_idx, opts ? opts->row_order : VBCSR_ORDER_AUTO, plan,
+             with_columns);
   return VBCSR_OK;
 }
 
@@ -284,7 +286,8 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA))
     return fail(VBCSR_EINVAL, "invalid plan options");
   HostPlan plan;
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
+  // column tables are built on the device from the per-block maps
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan, false);
   if (rc) return rc;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -320,11 +323,26 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     D.n_values = P.n_values;
     D.n_values16 = P.n_values16;
     if ((rc = upload_into(A, &D.rows, P.rows, s))) return bail(rc);
-    if ((rc = upload_into(A, &D.colx, P.colx, s))) return bail(rc);
+    if ((rc = alloc_into(A, &D.colx, (size_t)P.n_cols))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_k0, P.blk_k0, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_prow, P.blk_prow, s))) return bail(rc);
-    if (d == 0 && (rc = upload_into(A, &D.colg, P.colg, s))) return bail(rc);
+    if (d == 0 && (rc = alloc_into(A, &D.colg, (size_t)P.n_cols))) return bail(rc);
+    {
+      ColumnParams cp{};
+      cp.rows = D.rows;
+      cp.prow = D.blk_prow;
+      cp.k0 = D.blk_k0;
+      cp.catom = d == 0 ? A->col_idx : A->blk_row;
+      cp.b = A->b;
+      cp.off = A->off;
+      cp.gbase = d == 0 ? A->gbase : nullptr;
+      cp.nnzb = A->nnzb;
+      cp.colx = D.colx;
+      cp.colg = d == 0 ? D.colg : nullptr;
+      hipError_t e = launch_columns(cp, s);
+      if (e != hipSuccess) return bail(hip_fail(e, "column table kernel launch"));
+    }
     if (prec == VBCSR_BF16X3) {
       if ((rc = upload_into(A, &D.vbase16, P.vbase16, s))) return bail(rc);
       if ((rc = alloc_into(A, &D.hi, (size_t)P.n_values16))) return bail(rc);
@@ -420,7 +438,7 @@ int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *
                     int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values,
                     const vbcsr_plan_opts *opts) {
   HostPlan plan;
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan);
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan, false);
   if (rc) return rc;
   if (n_shapes) *n_shapes = (int32_t)plan.shapes.size();
   if (shapes)

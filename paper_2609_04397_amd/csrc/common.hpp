@@ -64,9 +64,12 @@ struct HostPlan {
 int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                    int64_t n_values, std::string &err);
 
-// Build both directions of the plan (assumes validate_graph passed).
+// Build both directions of the plan (assumes validate_graph passed).  With
+// with_columns unset the column tables (colx, colg) are left empty and only
+// their sizes (n_cols) are set; the device builds them from the per-block
+// maps (blk_prow, blk_k0).
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                int32_t row_order, HostPlan &plan);
+                int32_t row_order, HostPlan &plan, bool with_columns = true);
 
 // Symbolic stage of the thresholded block product C = A B over one atom set
 // (host).  Candidates of row i are the columns j of the rows k of B with a

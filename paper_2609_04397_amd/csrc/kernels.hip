@@ -1516,6 +1516,21 @@ __global__ void __launch_bounds__(kThreads) k_kpm_dos(const double *c, int M, co
   if (i < np) rho[i] = s / (M_PI * sqrt(1.0 - xi * xi));
 }
 
+// One thread per graph block writes the column-table entries of its panel
+// columns (set-up, once per structure).
+__global__ void __launch_bounds__(kThreads) k_columns(ColumnParams P) {
+  const int64_t k = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (k >= P.nnzb) return;
+  const int32_t c = P.catom[k];
+  const int bc = P.b[c];
+  const int64_t base = P.rows[P.prow[k]].cbase + P.k0[k];
+  const int32_t o = P.off[c];
+  for (int q = 0; q < bc; ++q) {
+    P.colx[base + q] = o + q;
+    if (P.colg) P.colg[base + q] = ((P.gbase[k] + q) << 7) | bc;
+  }
+}
+
 }  // namespace
 
 int64_t product_workgroups(int64_t nrows) { return (nrows + kWaves - 1) / kWaves; }
@@ -1647,6 +1662,13 @@ hipError_t launch_kpm_dos(const double *mu, int M, int damping, const double *x,
   if (e != hipSuccess || np == 0) return e;
   hipLaunchKernelGGL(k_kpm_dos, dim3((unsigned)((np + kThreads - 1) / kThreads)), dim3(kThreads), 0,
                      s, coef, M, x, np, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_columns(const ColumnParams &p, hipStream_t s) {
+  if (p.nnzb == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_columns, dim3((unsigned)((p.nnzb + kThreads - 1) / kThreads)), dim3(kThreads),
+                     0, s, p);
   return hipGetLastError();
 }
 

@@ -141,4 +141,20 @@ hipError_t launch_unpack(const void *pages, int elem_bytes, const int64_t *pos,
 hipError_t launch_kpm_dos(const double *mu, int M, int damping, const double *x, int64_t np,
                           double *coef, double *rho, hipStream_t s);
 
+// Column tables of one direction from the per-block maps: graph block k
+// fills the b_c entries of its panel columns, starting at
+// rows[prow[k]].cbase + k0[k], with colx = off[c] + q and (forward only,
+// colg != null) colg = (gbase[k] + q) << 7 | b_c, where c = catom[k] is the
+// atom indexing the block's panel columns (forward: its column, adjoint: its
+// row).
+struct ColumnParams {
+  const RowDesc *rows;
+  const int32_t *prow, *k0, *catom, *b, *off;
+  const int64_t *gbase;
+  int64_t nnzb;
+  int32_t *colx;
+  int64_t *colg;
+};
+hipError_t launch_columns(const ColumnParams &p, hipStream_t s);
+
 }  // namespace vbcsr

@@ -149,7 +149,7 @@ static void sort_members(int32_t n, const int32_t *b, Members &M) {
 // values and column-table entries contiguous.
 static void layout_direction(int32_t n, const int32_t *b, const std::vector<int64_t> &off,
                              const Members &M, int64_t nnzb, const std::vector<int64_t> *gbase,
-                             const std::vector<int32_t> &order, DirPlan &d) {
+                             const std::vector<int32_t> &order, bool with_columns, DirPlan &d) {
   d.rows.resize(n);
   d.vbase16.resize(n);
   d.blk_pos.assign(nnzb, 0);
@@ -185,8 +185,10 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
   d.n_values = vbase;
   d.n_cols = cbase;
   d.n_values16 = vbase16;
-  d.colx.assign(cbase, 0);
-  if (gbase) d.colg.assign(cbase, 0);
+  if (with_columns) {
+    d.colx.assign(cbase, 0);
+    if (gbase) d.colg.assign(cbase, 0);
+  }
   parallel_rows(n, [&](int32_t p0, int32_t p1) {
     for (int32_t pi = p0; pi < p1; ++pi) {
       const int32_t r = order[pi];
@@ -198,10 +200,11 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
         d.blk_pos[k] = rd.vbase + (int64_t)k0 * rd.b;
         d.blk_k0[k] = k0;
         d.blk_prow[k] = pi;
-        for (int32_t q = 0; q < b[c]; ++q) {
-          d.colx[rd.cbase + k0 + q] = (int32_t)(off[c] + q);
-          if (gbase) d.colg[rd.cbase + k0 + q] = (((*gbase)[k] + q) << 7) | b[c];
-        }
+        if (with_columns)
+          for (int32_t q = 0; q < b[c]; ++q) {
+            d.colx[rd.cbase + k0 + q] = (int32_t)(off[c] + q);
+            if (gbase) d.colg[rd.cbase + k0 + q] = (((*gbase)[k] + q) << 7) | b[c];
+          }
         k0 += b[c];
       }
     }
@@ -263,7 +266,7 @@ static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const i
 }
 
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                int32_t row_order, HostPlan &plan) {
+                int32_t row_order, HostPlan &plan, bool with_columns) {
   plan.n = n;
   plan.off.assign((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) plan.off[i + 1] = plan.off[i] + b[i];
@@ -316,7 +319,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   M.mblk.resize(nnzb);
   std::iota(M.mblk.begin(), M.mblk.end(), int64_t(0));
   sort_members(n, b, M);
-  layout_direction(n, b, plan.off, M, nnzb, &plan.gbase, order, plan.fwd);
+  layout_direction(n, b, plan.off, M, nnzb, &plan.gbase, order, with_columns, plan.fwd);
 
   // transposed: panel j holds the blocks (i, j) of block column j, ordered by (b_i, i)
   std::fill(M.mptr.begin(), M.mptr.end(), 0);
@@ -332,7 +335,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
       }
   }
   sort_members(n, b, M);
-  layout_direction(n, b, plan.off, M, nnzb, nullptr, order, plan.tr);
+  layout_direction(n, b, plan.off, M, nnzb, nullptr, order, with_columns, plan.tr);
 }
 
 }  // namespace vbcsr
