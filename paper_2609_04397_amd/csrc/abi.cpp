@@ -63,8 +63,8 @@ int dev_alloc(void **p, size_t bytes) {
   return VBCSR_OK;
 }
 
-template <typename T>
-int upload(T **dst, const std::vector<T> &src, hipStream_t s) {
+template <typename T, typename Alloc>
+int upload(T **dst, const std::vector<T, Alloc> &src, hipStream_t s) {
   int rc = dev_alloc(reinterpret_cast<void **>(dst), sizeof(T) * src.size());
   if (rc) return rc;
   if (!src.empty())
@@ -403,8 +403,8 @@ struct TempAllocs {
     if (rc == VBCSR_OK && *p) ptrs.push_back(*p);
     return rc;
   }
-  template <typename T>
-  int up(T **p, const std::vector<T> &v, hipStream_t s) {
+  template <typename T, typename Alloc>
+  int up(T **p, const std::vector<T, Alloc> &v, hipStream_t s) {
     int rc = upload(p, v, s);
     if (rc == VBCSR_OK && *p) ptrs.push_back(*p);
     return rc;
@@ -882,7 +882,7 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   // final block-norm filter: drop computed blocks whose norm is below eps
   t0 = clk::now();
   std::vector<int64_t> crp(plan.row_ptr);
-  std::vector<int32_t> ccol(plan.oj);
+  std::vector<int32_t> ccol(plan.oj.begin(), plan.oj.end());
   const double *final_vals = cvals;
   int64_t final_nvals = nvals;
   if (eps > 0.0 && nC > 0) {

@@ -4,7 +4,9 @@
 
 #include <array>
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace vbcsr {
@@ -71,6 +73,29 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                 int32_t row_order, HostPlan &plan, bool with_columns = true);
 
+// A std::vector whose new elements are left uninitialised: large host
+// buffers are then first written (and paged in) by the threads that fill
+// them instead of being zeroed by one thread.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U> &) {}
+  template <typename U, typename... Args>
+  void construct(U *p, Args &&...args) {
+    if constexpr (sizeof...(Args) == 0)
+      ::new (static_cast<void *>(p)) U;
+    else
+      ::new (static_cast<void *>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <typename T>
+using RawVec = std::vector<T, NoInitAlloc<T>>;
+
 // Symbolic stage of the thresholded block product C = A B over one atom set
 // (host).  Candidates of row i are the columns j of the rows k of B with a
 // block (i, k) in A; each carries the bound U_ij = sum_k ||A_ik|| ||B_kj||
@@ -80,12 +105,12 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
 struct SpgemmPlan {
   int64_t candidates = 0;        // distinct (i, j) reached through some k
   std::vector<int64_t> row_ptr;  // n+1, over kept blocks
-  std::vector<int32_t> oi, oj;   // per kept block: row and column atom
-  std::vector<double> bound;     // per kept block: U_ij (0 when no norms)
-  std::vector<int64_t> obase;    // per kept block + 1: graph-order value offsets
-  std::vector<int64_t> pptr;     // per kept block + 1: product ranges
-  std::vector<int64_t> pa;       // per product: apos of A_ik << 8 | b_k
-  std::vector<int64_t> pb;       // per product: bpos of B_kj
+  RawVec<int32_t> oi, oj;        // per kept block: row and column atom
+  RawVec<double> bound;          // per kept block: U_ij (0 when no norms)
+  RawVec<int64_t> obase;         // per kept block + 1: graph-order value offsets
+  RawVec<int64_t> pptr;          // per kept block + 1: product ranges
+  RawVec<int64_t> pa;            // per product: apos of A_ik << 8 | b_k
+  RawVec<int64_t> pb;            // per product: bpos of B_kj
   double flops = 0.0;            // sum over products of 2 b_i b_k b_j
 };
 

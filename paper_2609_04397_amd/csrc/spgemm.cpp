@@ -129,13 +129,15 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
     out.flops += fl[i];
   }
   const int64_t nC = out.row_ptr[n], nP = prow[n];
-  out.oi.assign(nC, 0);
-  out.oj.assign(nC, 0);
-  out.bound.assign(nC, 0.0);
-  out.obase.assign(nC + 1, 0);
-  out.pptr.assign(nC + 1, 0);
-  out.pa.assign(nP, 0);
-  out.pb.assign(nP, 0);
+  // every entry below is written exactly once by pass 2 (and the final
+  // offsets), so the buffers are not cleared first
+  out.oi.resize(nC);
+  out.oj.resize(nC);
+  out.bound.resize(nC);
+  out.obase.resize(nC + 1);
+  out.pptr.resize(nC + 1);
+  out.pa.resize(nP);
+  out.pb.resize(nP);
   // value offsets need the running sum over rows of b_i * sum b_j
   std::vector<int64_t> vsum(n, 0);
 
