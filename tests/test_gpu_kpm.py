@@ -102,3 +102,28 @@ def test_pipeline_gap_of_block_operator():
     top_lo, bot_hi = lam_all[lam_all < 0].max(), lam_all[lam_all > 0].min()
     sigma = np.pi / M
     assert abs(g[0] - top_lo) < 6 * sigma and abs(g[1] - bot_hi) < 6 * sigma
+
+
+def test_pipeline_with_doubled_moments():
+    """Moment doubling (half the products) feeds the same density: the
+    doubled and the plain moments give densities within rounding."""
+    rng = np.random.default_rng(12)
+    b = np.array([9, 13, 4] * 20, dtype=np.int32)
+    vals, n = [], b.size
+    for bi in b:
+        lam = rng.uniform(-0.9, 0.9, bi)
+        Q, _ = np.linalg.qr(rng.standard_normal((bi, bi)))
+        vals.append((Q @ np.diag(lam) @ Q.T).ravel())
+    op = Operator("diag-blocks", b, np.arange(n + 1, dtype=np.int64), np.arange(n, dtype=np.int32),
+                  np.concatenate(vals), np.zeros(n))
+    A = Matrix.from_operator(op)
+    R = torch.from_numpy(rng.standard_normal((op.N, 8))).cuda()
+    M = 128
+    mu_p = A.cheb_moments(R, M - 1).sum(axis=1) / (op.N * 8)
+    mu_d = A.cheb_moments(R, M - 1, doubled=True).sum(axis=1) / (op.N * 8)
+    assert np.max(np.abs(mu_p - mu_d)) <= 1e-12
+    x = np.linspace(-0.99, 0.99, 2001)
+    rp = kpm.dos(d(mu_p), d(x)).cpu().numpy()
+    rd = kpm.dos(d(mu_d), d(x)).cpu().numpy()
+    assert np.max(np.abs(rp - rd)) <= 1e-10 * np.max(np.abs(rp))
+    check_dos(mu_d, x, "jackson", rd)

@@ -147,3 +147,18 @@ def test_errors_and_empty():
     E.sample([0.1, 0.1, 0.1])
     Y = E.spmm(torch.ones(5, 2, dtype=torch.complex128, device="cuda"))
     assert float(Y.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_largest_blocks_and_many_rhs(prec):
+    """b up to 64 (4 matrix-core row tiles, one column group per step) and
+    64 right-hand sides (4 tiles per pass)."""
+    Z = random_images(21, 12, bset=(1, 33, 64, 16), density=0.35, hermitian=False)
+    rng = np.random.default_rng(4)
+    KM = KMatrix.from_images(Z, prec=prec)
+    k = rng.uniform(-1, 1, 3)
+    KM.sample(k, "R+tau")
+    K = KOperator(Z, k, "R+tau")
+    for nrhs in (5, 64):
+        X = rng.standard_normal((Z.N, nrhs)) + 1j * rng.standard_normal((Z.N, nrhs))
+        check_products(Z, K, KM, X, prec)

@@ -214,3 +214,17 @@ def test_spgemm_g1_full_size_sampled(eps):
     if eps > 0:   # the threshold acts in both stages at this size
         assert st["kept_symbolic"] < st["candidates"] and st["nnzb"] < st["kept_symbolic"]
     print("G1 stats", st, flush=True)
+
+
+def test_spgemm_result_planned_in_rcm_order():
+    """C planned in reverse Cuthill-McKee order: same blocks and values, and
+    its products agree with the atom-order plan."""
+    op = make_operator("C5", 0.01)
+    A = Matrix.from_operator(op)
+    C1, _ = A.spgemm(A, 0.0, row_order="atom")
+    C2, _ = A.spgemm(A, 0.0, row_order="rcm")
+    assert np.array_equal(C1.row_ptr, C2.row_ptr) and np.array_equal(C1.col_idx, C2.col_idx)
+    assert torch.equal(C1.values(), C2.values())
+    X = torch.randn(op.N, 9, dtype=torch.float64, device="cuda")
+    assert torch.equal(C1.spmm(X), C2.spmm(X))
+    compare(op, op, 0.0, C2, C2.values().cpu().numpy())
