@@ -17,7 +17,9 @@
  *
  * Errors: every call returns a status (VBCSR_OK or a negative code) and
  * records a message readable through vbcsr_last_error() on the calling
- * thread.  All argument validation happens on the host before any HIP call.
+ * thread.  All argument validation happens on the host before any HIP call
+ * (vbcsr_spgemm copies the two handles' block sizes back to compare them,
+ * before any kernel runs).
  * Asynchronous device faults are reported as VBCSR_EHIP by a later call.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
