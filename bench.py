@@ -433,7 +433,7 @@ def run_sweep(path):
 
 def kspace_records():
     """Reciprocal-space form of the 100k-atom cube (C5 as a periodic cell:
-    every block carries its minimum-image shift, 27 images): sampling O(k)
+    every block carries its minimum-image shift, 21 images): sampling O(k)
     (R+tau convention) and complex products with O(k) and O(k)^H, FP64.
     Algorithmic bytes: sampling reads the real values (8 B each) and writes
     both complex pages (2 x 16 B per value); a product reads the complex

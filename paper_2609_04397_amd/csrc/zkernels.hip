@@ -20,13 +20,13 @@ __device__ __forceinline__ int wave_id() {
 }
 
 __global__ void __launch_bounds__(kThreads) k_zphase(ZPhaseParams P) {
-  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (t >= P.nnzb) return;
-  const int32_t *R = P.shifts + 3 * (int64_t)P.image[t];
+  const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (c >= P.n) return;
+  const int32_t *R = P.shifts + 3 * (int64_t)P.image[c];
   double d0 = R[0], d1 = R[1], d2 = R[2];
   if (P.tau) {
-    const double *tj = P.tau + 3 * (int64_t)P.col_idx[t];
-    const double *ti = P.tau + 3 * (int64_t)P.blk_row[t];
+    const double *tj = P.tau + 3 * (int64_t)P.col_idx[c];
+    const double *ti = P.tau + 3 * (int64_t)P.blk_row[c];
     d0 += tj[0] - ti[0];
     d1 += tj[1] - ti[1];
     d2 += tj[2] - ti[2];
@@ -34,34 +34,85 @@ __global__ void __launch_bounds__(kThreads) k_zphase(ZPhaseParams P) {
   const double th = -2.0 * M_PI * (P.k[0] * d0 + P.k[1] * d1 + P.k[2] * d2);
   double sn, cs;
   sincos(th, &sn, &cs);
-  P.ph[2 * t] = cs;
-  P.ph[2 * t + 1] = sn;
+  P.ph[2 * c] = cs;
+  P.ph[2 * c + 1] = sn;
 }
 
+// Values in flight per lane in the sampling kernel.
+constexpr int kSampleBatch = 8;
+
+// The wave's blocks are kb0 .. kb0 + nb - 1, their values numbered 0 .. T-1
+// in graph order; lane l takes values l, l + 64, ... in batches whose value
+// and phase loads are all issued before the first use.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_zsample(ZSampleParams P, T *fwd, T *tr) {
-  const int64_t kb = (int64_t)blockIdx.x * kWaves + wave_id();
-  if (kb >= P.nkb) return;
+  using V2 = typename C2<T>::type;
+  const int64_t kb0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kSampleBlocks;
+  if (kb0 >= P.nkb) return;
   const int lane = threadIdx.x & 63;
-  const int bi = P.b[P.krow[kb]], bj = P.b[P.kcol[kb]];
-  const int64_t c0 = P.cptr[kb], c1 = P.cptr[kb + 1];
-  T *f = fwd + 2 * P.fwd_pos[kb];
-  T *g = tr + 2 * P.tr_pos[kb];
-  for (int e = lane; e < bi * bj; e += 64) {
-    double re = 0.0, im = 0.0;
-    for (int64_t c = c0; c < c1; ++c) {
-      const int64_t t = P.cblk[c];
-      const double v = P.values[P.gbase[t] + e];
-      re = fma(v, P.ph[2 * t], re);
-      im = fma(v, P.ph[2 * t + 1], im);
+  const int nb = (int)min((int64_t)kSampleBlocks, P.nkb - kb0);
+  // lane j < nb holds block kb0 + j; lane nb reads the end of the last block
+  int d = 0, cnt = 0;
+  int64_t base = 0, vb = 0, c0 = 0, fp = 0, tp = 0;
+  if (lane <= nb) base = P.kbase[kb0 + lane];
+  if (lane < nb) {
+    const int64_t kb = kb0 + lane;
+    d = P.kdim[kb];
+    c0 = P.cptr[kb];
+    cnt = (int)(P.cptr[kb + 1] - c0);
+    vb = P.kvbase[kb];
+    fp = P.fwd_pos[kb];
+    tp = P.tr_pos[kb];
+  }
+  const int rel = (int)(base - __shfl(base, 0));  // value offset of lane j's block
+  const int total = __builtin_amdgcn_readlane(rel, nb);
+  int start[kSampleBlocks];
+#pragma unroll
+  for (int k = 0; k < kSampleBlocks; ++k)
+    start[k] = k <= nb ? __builtin_amdgcn_readlane(rel, k) : total;
+  const double2 *ph = reinterpret_cast<const double2 *>(P.ph);
+  for (int v0 = 0; v0 < total; v0 += 64 * kSampleBatch) {
+    double x[kSampleBatch];
+    double2 w[kSampleBatch];
+    int jv[kSampleBatch], ev[kSampleBatch];
+#pragma unroll
+    for (int u = 0; u < kSampleBatch; ++u) {
+      const int v = v0 + 64 * u + lane;
+      int j = 0;
+#pragma unroll
+      for (int k = 1; k < kSampleBlocks; ++k) j += start[k] <= v ? 1 : 0;
+      jv[u] = j;
+      ev[u] = v - __shfl(rel, j);
+      const int64_t vbj = __shfl(vb, j), c0j = __shfl(c0, j);
+      x[u] = 0.0;
+      w[u] = make_double2(0.0, 0.0);
+      if (v < total) {
+        x[u] = P.values[vbj + ev[u]];
+        w[u] = ph[c0j];
+      }
     }
-    const int p = e / bj, q = e - p * bj;
-    const int64_t af = 2 * ((int64_t)q * bi + p);   // column-major in the forward panel
-    const int64_t at = 2 * (int64_t)e;              // row-major (= A^H column-major)
-    f[af] = (T)re;
-    f[af + 1] = (T)im;
-    g[at] = (T)re;
-    g[at + 1] = (T)(-im);
+#pragma unroll
+    for (int u = 0; u < kSampleBatch; ++u) {
+      const int v = v0 + 64 * u + lane, j = jv[u], e = ev[u];
+      const int dj = __shfl(d, j), cj = __shfl(cnt, j);
+      const int64_t c0j = __shfl(c0, j), fj = __shfl(fp, j), tj = __shfl(tp, j);
+      if (v >= total) continue;
+      double re = x[u] * w[u].x, im = x[u] * w[u].y;
+      for (int64_t c = c0j + 1; c < c0j + cj; ++c) {  // further images of the block
+        const double y = P.values[P.cgbase[c] + e];
+        const double2 z = ph[c];
+        re = fma(y, z.x, re);
+        im = fma(y, z.y, im);
+      }
+      const int bi = dj & 0xffff, bj = dj >> 16;
+      const int p = e / bj, q = e - p * bj;
+      V2 o;
+      o.x = (T)re;
+      o.y = (T)im;
+      *reinterpret_cast<V2 *>(fwd + 2 * (fj + (int64_t)q * bi + p)) = o;  // column-major
+      o.y = (T)(-im);
+      *reinterpret_cast<V2 *>(tr + 2 * (tj + (int64_t)e)) = o;  // row-major (= A^H column-major)
+    }
   }
 }
 
@@ -285,8 +336,8 @@ hipError_t launch_zspmm_t(const ZSpmmParams<T> &p, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_zphase(const ZPhaseParams &p, hipStream_t s) {
-  if (p.nnzb == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_zphase, dim3((unsigned)((p.nnzb + kThreads - 1) / kThreads)),
+  if (p.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zphase, dim3((unsigned)((p.n + kThreads - 1) / kThreads)),
                      dim3(kThreads), 0, s, p);
   return hipGetLastError();
 }
@@ -294,7 +345,8 @@ hipError_t launch_zphase(const ZPhaseParams &p, hipStream_t s) {
 hipError_t launch_zsample(const ZSampleParams &p, void *fwd, void *tr, int elem_bytes,
                           hipStream_t s) {
   if (p.nkb == 0) return hipSuccess;
-  const dim3 grid((unsigned)((p.nkb + kWaves - 1) / kWaves));
+  const int64_t waves = (p.nkb + kSampleBlocks - 1) / kSampleBlocks;
+  const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves));
   if (elem_bytes == 8)
     hipLaunchKernelGGL(k_zsample<double>, grid, dim3(kThreads), 0, s, p,
                        static_cast<double *>(fwd), static_cast<double *>(tr));

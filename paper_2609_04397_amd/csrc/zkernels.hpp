@@ -9,8 +9,9 @@
 
 namespace vbcsr {
 
-// Per real block t: ph[2t], ph[2t+1] = cos, sin of -2 pi k . d_t with
-// d_t = shifts[image[t]] (+ tau[col_t] - tau[row_t] when tau is given).
+// Per contribution c (a real block, listed by the block of O(k) it adds to):
+// ph[2c], ph[2c+1] = cos, sin of -2 pi k . d_c with d_c = shifts[image[c]]
+// (+ tau[col_idx[c]] - tau[blk_row[c]] when tau is given).
 struct ZPhaseParams {
   const int32_t *image;
   const int32_t *blk_row;
@@ -18,24 +19,27 @@ struct ZPhaseParams {
   const int32_t *shifts;  // [n_images * 3]
   const double *tau;      // [n * 3] or null
   double k[3];
-  int64_t nnzb;
+  int64_t n;               // contributions
   double *ph;
 };
 
-// One wave per block kb of O(k): the sum over its real blocks
-// t = cblk[cptr[kb] .. cptr[kb+1]) of ph_t * values[gbase[t] ..] (row-major
-// b_i x b_j), written column-major at fwd_pos[kb] of the forward pages and,
-// conjugated and row-major, at tr_pos[kb] of the adjoint pages (complex
-// elements of type T).
+// Block kb of O(k) is the sum over its contributions c in [cptr[kb],
+// cptr[kb+1]) of ph_c * values[cgbase[c] ..] (row-major b_i x b_j), written
+// column-major at fwd_pos[kb] of the forward pages and, conjugated and
+// row-major, at tr_pos[kb] of the adjoint pages (complex elements of type T).
+// One wave takes kSampleBlocks consecutive blocks; kvbase[kb] is
+// cgbase[cptr[kb]], so a block's first contribution needs no further lookup.
+constexpr int kSampleBlocks = 8;
 struct ZSampleParams {
-  const int32_t *b;
-  const int32_t *krow, *kcol;
-  const int64_t *cptr, *cblk;
-  const int64_t *gbase;
-  const double *values;
-  const double *ph;
-  const int64_t *fwd_pos, *tr_pos;
   int64_t nkb;
+  const int32_t *kdim;    // per block: b_i | b_j << 16
+  const int64_t *kbase;   // [nkb + 1] offset of each block's first value, graph order
+  const int64_t *kvbase;  // per block
+  const int64_t *cptr;    // [nkb + 1]
+  const int64_t *cgbase;  // per contribution
+  const double *values;
+  const double *ph;       // per contribution: cos, sin
+  const int64_t *fwd_pos, *tr_pos;
 };
 
 // Y = alpha * op(O) X + beta * Y over the panels of one direction (complex,

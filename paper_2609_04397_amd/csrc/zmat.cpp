@@ -25,9 +25,9 @@ struct vbcsr_zmat {
   std::vector<int32_t> kci_host;
   // device
   int32_t *b = nullptr, *image = nullptr, *blk_row = nullptr, *col_idx = nullptr;
-  int32_t *shifts = nullptr, *krow = nullptr, *kcol = nullptr;
+  int32_t *shifts = nullptr, *krow = nullptr, *kcol = nullptr, *kdim = nullptr;
   double *tau = nullptr, *values = nullptr, *ph = nullptr;
-  int64_t *gbase = nullptr, *cptr = nullptr, *cblk = nullptr, *kbase = nullptr;
+  int64_t *cgbase = nullptr, *cptr = nullptr, *kbase = nullptr, *kvbase = nullptr;
   RowDesc *rows[2] = {nullptr, nullptr};
   int32_t *colx[2] = {nullptr, nullptr};
   int64_t *pos[2] = {nullptr, nullptr};
@@ -188,6 +188,23 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
     std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
     for (int64_t t = 0; t < nnzb; ++t) cblk[fill[kb_of[t]]++] = t;
   }
+  // what the phase and sample kernels read per contribution
+  std::vector<int32_t> cimage(nnzb), crow(nnzb), ccol(nnzb);
+  std::vector<int64_t> cgbase(nnzb);
+  for (int64_t c = 0; c < nnzb; ++c) {
+    const int64_t t = cblk[c];
+    cimage[c] = image[t];
+    crow[c] = brow[t];
+    ccol[c] = col_idx[t];
+    cgbase[c] = gbase[t];
+  }
+  // per block of O(k): its sizes and where its first contribution's values start
+  std::vector<int32_t> kdim(nkb);
+  std::vector<int64_t> kvbase(nkb);
+  for (int64_t c = 0; c < nkb; ++c) {
+    kdim[c] = block_sizes[krow[c]] | block_sizes[kci[c]] << 16;
+    kvbase[c] = cgbase[cptr[c]];
+  }
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   vbcsr_zmat *Z = new vbcsr_zmat();
@@ -208,17 +225,18 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
     return code;
   };
   if ((rc = zup(Z, &Z->b, block_sizes, (size_t)n_atoms, s)) ||
-      (rc = zup(Z, &Z->image, image, (size_t)nnzb, s)) ||
-      (rc = zup(Z, &Z->blk_row, brow.data(), (size_t)nnzb, s)) ||
-      (rc = zup(Z, &Z->col_idx, col_idx, (size_t)nnzb, s)) ||
+      (rc = zup(Z, &Z->image, cimage.data(), (size_t)nnzb, s)) ||
+      (rc = zup(Z, &Z->blk_row, crow.data(), (size_t)nnzb, s)) ||
+      (rc = zup(Z, &Z->col_idx, ccol.data(), (size_t)nnzb, s)) ||
       (rc = zup(Z, &Z->shifts, shifts, (size_t)n_images * 3, s)) ||
       (tau && (rc = zup(Z, &Z->tau, tau, (size_t)n_atoms * 3, s))) ||
-      (rc = zup(Z, &Z->gbase, gbase.data(), (size_t)nnzb, s)) ||
+      (rc = zup(Z, &Z->cgbase, cgbase.data(), (size_t)nnzb, s)) ||
       (rc = zup(Z, &Z->cptr, cptr.data(), (size_t)nkb + 1, s)) ||
-      (rc = zup(Z, &Z->cblk, cblk.data(), (size_t)nnzb, s)) ||
+      (rc = zup(Z, &Z->kdim, kdim.data(), (size_t)nkb, s)) ||
+      (rc = zup(Z, &Z->kvbase, kvbase.data(), (size_t)nkb, s)) ||
       (rc = zup(Z, &Z->krow, krow.data(), (size_t)nkb, s)) ||
       (rc = zup(Z, &Z->kcol, kci.data(), (size_t)nkb, s)) ||
-      (rc = zup(Z, &Z->kbase, kbase.data(), (size_t)nkb, s)) ||
+      (rc = zup(Z, &Z->kbase, kbase.data(), (size_t)nkb + 1, s)) ||
       (rc = zalloc(Z, &Z->values, (size_t)nnz)) || (rc = zalloc(Z, &Z->ph, (size_t)nnzb * 2)))
     return bail(rc);
   if (nnz) {
@@ -265,22 +283,21 @@ int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *
   pp.k[0] = k[0];
   pp.k[1] = k[1];
   pp.k[2] = k[2];
-  pp.nnzb = Z->nnzb;
+  pp.n = Z->nnzb;
   pp.ph = Z->ph;
   hipError_t e = launch_zphase(pp, s);
   if (e != hipSuccess) return zhip(e, "phase kernel launch");
   ZSampleParams sp{};
-  sp.b = Z->b;
-  sp.krow = Z->krow;
-  sp.kcol = Z->kcol;
+  sp.nkb = Z->nkb;
+  sp.kdim = Z->kdim;
+  sp.kvbase = Z->kvbase;
+  sp.kbase = Z->kbase;
   sp.cptr = Z->cptr;
-  sp.cblk = Z->cblk;
-  sp.gbase = Z->gbase;
+  sp.cgbase = Z->cgbase;
   sp.values = Z->values;
   sp.ph = Z->ph;
   sp.fwd_pos = Z->pos[0];
   sp.tr_pos = Z->pos[1];
-  sp.nkb = Z->nkb;
   e = launch_zsample(sp, Z->pages[0], Z->pages[1], (int)celem(Z), s);
   if (e != hipSuccess) return zhip(e, "sample kernel launch");
   return VBCSR_OK;
