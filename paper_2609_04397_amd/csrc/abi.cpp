@@ -125,8 +125,8 @@ int alloc_into(vbcsr_mat *A, T **p, size_t count) {
   return rc;
 }
 
-template <typename T>
-int upload_into(vbcsr_mat *A, T **p, const std::vector<T> &v, hipStream_t s) {
+template <typename T, typename Alloc>
+int upload_into(vbcsr_mat *A, T **p, const std::vector<T, Alloc> &v, hipStream_t s) {
   int rc = upload(p, v, s);
   if (rc == VBCSR_OK && *p) A->owned.push_back(*p);
   return rc;

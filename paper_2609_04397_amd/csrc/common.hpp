@@ -37,42 +37,6 @@ static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 constexpr int64_t kPanelAlign = 4;
 constexpr int64_t kPageSlack = 2;
 
-struct DirPlan {
-  std::vector<RowDesc> rows;     // one per atom, in processing order
-  std::vector<int32_t> colx;     // per panel column: scalar row of the input vector
-  std::vector<int64_t> colg;     // forward only, per panel column: (graph offset of the
-                                 // column's block + q) << 7 | b_j (block-sampled product)
-  std::vector<int64_t> blk_pos;  // per graph block: page offset of its first value
-  std::vector<int32_t> blk_k0;   // per graph block: first panel column
-  std::vector<int32_t> blk_prow; // per graph block: index (processing order) of its panel
-  std::vector<int64_t> vbase16;  // per panel (processing order): offset in the BF16 pages
-  int64_t n_values = 0;          // values in the pages
-  int64_t n_values16 = 0;        // values in each BF16 page (panels padded to 8 columns)
-  int64_t n_cols = 0;            // entries of the column table
-};
-
-struct HostPlan {
-  int32_t n = 0;
-  int64_t N = 0, nnzb = 0, nnz = 0;
-  std::vector<int64_t> off;                   // n+1 scalar row offsets
-  std::vector<int64_t> gbase;                 // nnzb+1 graph value offsets
-  std::vector<int32_t> blk_row;               // per graph block: block row i
-  std::vector<std::array<int32_t, 3>> shapes; // (b_i, b_j, count), ascending
-  DirPlan fwd, tr;
-};
-
-// Host-side validation of a block graph; returns a VBCSR_* status and fills
-// `err` on failure.  Touches no device.
-int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                   int64_t n_values, std::string &err);
-
-// Build both directions of the plan (assumes validate_graph passed).  With
-// with_columns unset the column tables (colx, colg) are left empty and only
-// their sizes (n_cols) are set; the device builds them from the per-block
-// maps (blk_prow, blk_k0).
-void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                int32_t row_order, HostPlan &plan, bool with_columns = true);
-
 // A std::vector whose new elements are left uninitialised: large host
 // buffers are then first written (and paged in) by the threads that fill
 // them instead of being zeroed by one thread.
@@ -95,6 +59,43 @@ struct NoInitAlloc : std::allocator<T> {
 };
 template <typename T>
 using RawVec = std::vector<T, NoInitAlloc<T>>;
+
+struct DirPlan {
+  std::vector<RowDesc> rows;     // one per atom, in processing order
+  std::vector<int32_t> colx;     // per panel column: scalar row of the input vector
+  std::vector<int64_t> colg;     // forward only, per panel column: (graph offset of the
+                                 // column's block + q) << 7 | b_j (block-sampled product)
+  RawVec<int64_t> blk_pos;       // per graph block: page offset of its first value
+  RawVec<int32_t> blk_k0;        // per graph block: first panel column
+  RawVec<int32_t> blk_prow;      // per graph block: index (processing order) of its panel
+  std::vector<int64_t> vbase16;  // per panel (processing order): offset in the BF16 pages
+  int64_t n_values = 0;          // values in the pages
+  int64_t n_values16 = 0;        // values in each BF16 page (panels padded to 8 columns)
+  int64_t n_cols = 0;            // entries of the column table
+};
+
+struct HostPlan {
+  int32_t n = 0;
+  int64_t N = 0, nnzb = 0, nnz = 0;
+  std::vector<int64_t> off;                   // n+1 scalar row offsets
+  RawVec<int64_t> gbase;                      // nnzb+1 graph value offsets
+  RawVec<int32_t> blk_row;                    // per graph block: block row i
+  std::vector<std::array<int32_t, 3>> shapes; // (b_i, b_j, count), ascending
+  DirPlan fwd, tr;
+};
+
+// Host-side validation of a block graph; returns a VBCSR_* status and fills
+// `err` on failure.  Touches no device.
+int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
+                   int64_t n_values, std::string &err);
+
+// Build both directions of the plan (assumes validate_graph passed).  With
+// with_columns unset the column tables (colx, colg) are left empty and only
+// their sizes (n_cols) are set; the device builds them from the per-block
+// maps (blk_prow, blk_k0).
+void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
+                int32_t row_order, HostPlan &plan, bool with_columns = true);
+
 
 // Symbolic stage of the thresholded block product C = A B over one atom set
 // (host).  Candidates of row i are the columns j of the rows k of B with a

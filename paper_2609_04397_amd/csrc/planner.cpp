@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <thread>
 
@@ -121,25 +122,50 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 // mblk[...], sorted by (b of that atom, atom).
 struct Members {
   std::vector<int64_t> mptr;
-  std::vector<int32_t> mcol;
-  std::vector<int64_t> mblk;
+  RawVec<int32_t> mcol;
+  RawVec<int64_t> mblk;
 };
 
+// Sort every panel's members by (b, atom); the atoms of a panel are
+// distinct, so the order is unique.  A panel already ascending in the atom
+// is bucketed by b (stable), any other is sorted on packed keys.
 static void sort_members(int32_t n, const int32_t *b, Members &M) {
   parallel_rows(n, [&](int32_t r0, int32_t r1) {
-    std::vector<std::pair<int32_t, int64_t>> tmp;
+    std::vector<std::pair<uint64_t, int64_t>> keyed;
+    std::vector<int32_t> tcol;
+    std::vector<int64_t> tblk;
     for (int32_t r = r0; r < r1; ++r) {
-      const int64_t s0 = M.mptr[r], s1 = M.mptr[r + 1];
-      tmp.clear();
-      for (int64_t u = s0; u < s1; ++u) tmp.push_back({M.mcol[u], M.mblk[u]});
-      std::sort(tmp.begin(), tmp.end(), [&](const std::pair<int32_t, int64_t> &x,
-                                            const std::pair<int32_t, int64_t> &y) {
-        if (b[x.first] != b[y.first]) return b[x.first] < b[y.first];
-        return x.first < y.first;
-      });
-      for (int64_t u = s0; u < s1; ++u) {
-        M.mcol[u] = tmp[u - s0].first;
-        M.mblk[u] = tmp[u - s0].second;
+      const int64_t s0 = M.mptr[r], s1 = M.mptr[r + 1], len = s1 - s0;
+      if (len < 2) continue;
+      int32_t *col = M.mcol.data() + s0;
+      int64_t *blk = M.mblk.data() + s0;
+      bool ascending = true;
+      for (int64_t u = 1; u < len && ascending; ++u) ascending = col[u - 1] < col[u];
+      if (ascending) {
+        int64_t start[VBCSR_MAX_BLOCK + 2] = {};
+        for (int64_t u = 0; u < len; ++u) ++start[b[col[u]] + 1];
+        for (int v = 1; v <= VBCSR_MAX_BLOCK + 1; ++v) start[v] += start[v - 1];
+        tcol.resize(len);
+        tblk.resize(len);
+        for (int64_t u = 0; u < len; ++u) {
+          const int64_t t = start[b[col[u]]]++;
+          tcol[t] = col[u];
+          tblk[t] = blk[u];
+        }
+        std::copy(tcol.begin(), tcol.end(), col);
+        std::copy(tblk.begin(), tblk.end(), blk);
+      } else {
+        keyed.resize(len);
+        for (int64_t u = 0; u < len; ++u)
+          keyed[u] = {(uint64_t)b[col[u]] << 32 | (uint32_t)col[u], blk[u]};
+        std::sort(keyed.begin(), keyed.end(),
+                  [](const std::pair<uint64_t, int64_t> &x, const std::pair<uint64_t, int64_t> &y) {
+                    return x.first < y.first;
+                  });
+        for (int64_t u = 0; u < len; ++u) {
+          col[u] = (int32_t)(uint32_t)keyed[u].first;
+          blk[u] = keyed[u].second;
+        }
       }
     }
   });
@@ -148,13 +174,15 @@ static void sort_members(int32_t n, const int32_t *b, Members &M) {
 // Lay out one direction from its members: panels in `order`, each panel's
 // values and column-table entries contiguous.
 static void layout_direction(int32_t n, const int32_t *b, const std::vector<int64_t> &off,
-                             const Members &M, int64_t nnzb, const std::vector<int64_t> *gbase,
+                             const Members &M, int64_t nnzb, const RawVec<int64_t> *gbase,
                              const std::vector<int32_t> &order, bool with_columns, DirPlan &d) {
   d.rows.resize(n);
   d.vbase16.resize(n);
-  d.blk_pos.assign(nnzb, 0);
-  d.blk_k0.assign(nnzb, 0);
-  d.blk_prow.assign(nnzb, 0);
+  // every graph block belongs to exactly one panel: the fill below writes
+  // each entry once
+  d.blk_pos.resize(nnzb);
+  d.blk_k0.resize(nnzb);
+  d.blk_prow.resize(nnzb);
   // panel widths, then offsets in processing order (panels start on
   // 4-value boundaries, zero padding: a 16-byte load of values never mixes
   // two panels)
@@ -211,41 +239,109 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
   });
 }
 
+// Transposed block graph: column j holds the blocks (i, j), ascending in i.
+// Threads take contiguous row ranges; each counts its columns, the counts
+// give every range its own offsets within each column, and every range then
+// writes its blocks in row order, so the result does not depend on
+// threading.
+struct Transpose {
+  std::vector<int64_t> ptr;  // n+1
+  RawVec<int32_t> row;       // per entry: i
+  RawVec<int64_t> blk;       // per entry: graph block index of (i, j)
+};
+
+static void transpose_graph(int32_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                            Transpose &T) {
+  const int64_t nnzb = row_ptr[n];
+  T.ptr.assign((size_t)n + 1, 0);
+  T.row.resize(nnzb);
+  T.blk.resize(nnzb);
+  // ranges: at most 16, fewer when the per-range counts would pass 256 MiB
+  int64_t R = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 8192 || nnzb < 65536) R = 1;
+  R = std::max<int64_t>(1, std::min<int64_t>(R, (int64_t(256) << 20) / (8 * (int64_t)n + 8)));
+  std::vector<int32_t> rb((size_t)R + 1, n);
+  rb[0] = 0;
+  for (int64_t t = 1; t < R; ++t) {
+    const int64_t target = nnzb * t / R;
+    rb[t] = (int32_t)(std::upper_bound(row_ptr, row_ptr + n + 1, target) - row_ptr - 1);
+    rb[t] = std::max(rb[t], rb[t - 1]);
+  }
+  std::vector<int64_t> cnt((size_t)R * n, 0);
+  auto over_ranges = [&](auto &&body) {
+    std::vector<std::thread> th;
+    for (int64_t t = 1; t < R; ++t) th.emplace_back(body, t);
+    body(0);
+    for (auto &x : th) x.join();
+  };
+  over_ranges([&](int64_t t) {
+    int64_t *c = cnt.data() + t * n;
+    for (int64_t k = row_ptr[rb[t]]; k < row_ptr[rb[t + 1]]; ++k) ++c[col_idx[k]];
+  });
+  // column j: range 0's entries first, then range 1's, ...
+  int64_t base = 0;
+  for (int32_t j = 0; j < n; ++j) {
+    T.ptr[j] = base;
+    for (int64_t t = 0; t < R; ++t) {
+      const int64_t c = cnt[t * n + j];
+      cnt[t * n + j] = base;
+      base += c;
+    }
+  }
+  T.ptr[n] = base;
+  over_ranges([&](int64_t t) {
+    int64_t *at = cnt.data() + t * n;
+    for (int32_t i = rb[t]; i < rb[t + 1]; ++i)
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        const int64_t u = at[col_idx[k]]++;
+        T.row[u] = i;
+        T.blk[u] = k;
+      }
+  });
+}
+
 // Reverse Cuthill-McKee order of the symmetrised block graph: breadth-first
 // from a lowest-degree unvisited atom of each component, neighbours in
 // ascending degree, the whole sequence reversed.  Panels processed in this
 // order are graph neighbours of the panels processed just before them, so
-// the input rows they gather are still in the XCD's L2.
-static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const int32_t *col_idx) {
+// the input rows they gather are still in the XCD's L2.  The neighbours of
+// an atom are its off-diagonal blocks' atoms in its row and in its column (a
+// pair present in both directions counts twice); ties are broken by the
+// atom index.
+static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                                      const Transpose &T) {
   std::vector<int64_t> deg((size_t)n, 0);
-  for (int32_t i = 0; i < n; ++i)
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
-      if (col_idx[k] != i) {
-        ++deg[i];
-        ++deg[col_idx[k]];
-      }
+  parallel_rows(n, [&](int32_t r0, int32_t r1) {
+    for (int32_t i = r0; i < r1; ++i) {
+      int64_t d = (row_ptr[i + 1] - row_ptr[i]) + (T.ptr[i + 1] - T.ptr[i]);
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+        if (col_idx[k] == i) d -= 2;  // the diagonal block is in both lists
+      deg[i] = d;
+    }
+  });
   std::vector<int64_t> ap((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) ap[i + 1] = ap[i] + deg[i];
-  std::vector<int32_t> adj((size_t)ap[n]);
-  std::vector<int64_t> fill(ap.begin(), ap.end() - 1);
-  for (int32_t i = 0; i < n; ++i)
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-      const int32_t j = col_idx[k];
-      if (j == i) continue;
-      adj[fill[i]++] = j;
-      adj[fill[j]++] = i;
-    }
-  auto by_degree = [&](int32_t x, int32_t y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; };
+  // neighbour lists as (degree, atom) keys, sorted per atom
+  RawVec<uint64_t> adj((size_t)ap[n]);
+  auto key = [&](int32_t x) { return (uint64_t)deg[x] << 32 | (uint32_t)x; };
   parallel_rows(n, [&](int32_t r0, int32_t r1) {
-    for (int32_t i = r0; i < r1; ++i) std::sort(adj.begin() + ap[i], adj.begin() + ap[i + 1], by_degree);
+    for (int32_t i = r0; i < r1; ++i) {
+      int64_t u = ap[i];
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+        if (col_idx[k] != i) adj[u++] = key(col_idx[k]);
+      for (int64_t e = T.ptr[i]; e < T.ptr[i + 1]; ++e)
+        if (T.row[e] != i) adj[u++] = key(T.row[e]);
+      std::sort(adj.begin() + ap[i], adj.begin() + ap[i + 1]);
+    }
   });
-  std::vector<int32_t> starts((size_t)n);
-  std::iota(starts.begin(), starts.end(), 0);
-  std::sort(starts.begin(), starts.end(), by_degree);
+  std::vector<uint64_t> starts((size_t)n);
+  for (int32_t i = 0; i < n; ++i) starts[i] = key(i);
+  std::sort(starts.begin(), starts.end());
   std::vector<char> seen((size_t)n, 0);
   std::vector<int32_t> order;
   order.reserve((size_t)n);
-  for (int32_t s0 : starts) {
+  for (uint64_t sk : starts) {
+    const int32_t s0 = (int32_t)(uint32_t)sk;
     if (seen[s0]) continue;
     seen[s0] = 1;
     size_t head = order.size();
@@ -253,7 +349,7 @@ static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const i
     while (head < order.size()) {
       const int32_t v = order[head++];
       for (int64_t e = ap[v]; e < ap[v + 1]; ++e) {
-        const int32_t u = adj[e];
+        const int32_t u = (int32_t)(uint32_t)adj[e];
         if (!seen[u]) {
           seen[u] = 1;
           order.push_back(u);
@@ -273,41 +369,74 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   plan.N = plan.off[n];
   plan.nnzb = row_ptr[n];
   const int64_t nnzb = plan.nnzb;
-  plan.gbase.assign((size_t)nnzb + 1, 0);
-  plan.blk_row.assign((size_t)nnzb, 0);
-  // shape classes: b <= VBCSR_MAX_BLOCK, a dense table
+  // graph value offsets: per-row sums, a prefix over rows, then the rows
+  // in parallel; shape classes (b <= VBCSR_MAX_BLOCK) counted in a dense table
+  std::vector<int64_t> rowv((size_t)n + 1, 0);
   std::vector<int64_t> shape_count((VBCSR_MAX_BLOCK + 1) * (VBCSR_MAX_BLOCK + 1), 0);
-  for (int32_t i = 0; i < n; ++i)
-    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-      const int32_t j = col_idx[k];
-      plan.blk_row[k] = i;
-      plan.gbase[k + 1] = plan.gbase[k] + (int64_t)b[i] * b[j];
-      shape_count[b[i] * (VBCSR_MAX_BLOCK + 1) + b[j]] += 1;
+  parallel_rows(n, [&](int32_t r0, int32_t r1) {
+    int64_t cnt[VBCSR_MAX_BLOCK + 1];
+    for (int32_t i = r0; i < r1; ++i) {
+      std::fill(cnt, cnt + VBCSR_MAX_BLOCK + 1, 0);
+      int64_t v = 0;
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        ++cnt[b[col_idx[k]]];
+        v += (int64_t)b[i] * b[col_idx[k]];
+      }
+      rowv[i + 1] = v;
+      for (int32_t bj = 1; bj <= VBCSR_MAX_BLOCK; ++bj)
+        if (cnt[bj]) __atomic_fetch_add(&shape_count[b[i] * (VBCSR_MAX_BLOCK + 1) + bj], cnt[bj],
+                                        __ATOMIC_RELAXED);
     }
-  plan.nnz = plan.gbase[nnzb];
+  });
+  for (int32_t i = 0; i < n; ++i) rowv[i + 1] += rowv[i];
+  plan.gbase.resize((size_t)nnzb + 1);
+  plan.blk_row.resize((size_t)nnzb);
+  parallel_rows(n, [&](int32_t r0, int32_t r1) {
+    for (int32_t i = r0; i < r1; ++i) {
+      int64_t g = rowv[i];
+      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+        plan.blk_row[k] = i;
+        plan.gbase[k] = g;
+        g += (int64_t)b[i] * b[col_idx[k]];
+      }
+    }
+  });
+  plan.gbase[nnzb] = rowv[n];
+  plan.nnz = rowv[n];
   plan.shapes.clear();
   for (int32_t bi = 1; bi <= VBCSR_MAX_BLOCK; ++bi)
     for (int32_t bj = 1; bj <= VBCSR_MAX_BLOCK; ++bj)
       if (shape_count[bi * (VBCSR_MAX_BLOCK + 1) + bj])
         plan.shapes.push_back({bi, bj, (int32_t)shape_count[bi * (VBCSR_MAX_BLOCK + 1) + bj]});
+  Transpose T;
+  transpose_graph(n, row_ptr, col_idx, T);
   std::vector<int32_t> order((size_t)n);
   std::iota(order.begin(), order.end(), 0);
   if (row_order != VBCSR_ORDER_ATOM) {
-    std::vector<int32_t> rcm = rcm_order(n, row_ptr, col_idx);
+    std::vector<int32_t> rcm = rcm_order(n, row_ptr, col_idx, T);
     // AUTO keeps the caller's order unless RCM at least halves the mean
     // distance, in processing order, between the two atoms of a block
-    // (a lattice or a spatially sorted input already has locality)
+    // (a lattice or a spatially sorted input already has locality); the
+    // distances are summed exactly, in integers
     bool take = row_order == VBCSR_ORDER_RCM;
     if (!take && nnzb > 0) {
       std::vector<int32_t> pos((size_t)n);
       for (int32_t t = 0; t < n; ++t) pos[rcm[t]] = t;
-      double d_atom = 0.0, d_rcm = 0.0;
-      for (int32_t i = 0; i < n; ++i)
-        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-          d_atom += std::abs((double)i - (double)col_idx[k]);
-          d_rcm += std::abs((double)pos[i] - (double)pos[col_idx[k]]);
-        }
-      take = 2.0 * d_rcm <= d_atom;
+      unsigned __int128 d_atom = 0, d_rcm = 0;
+      std::mutex mu;
+      parallel_rows(n, [&](int32_t r0, int32_t r1) {
+        unsigned __int128 da = 0, dr = 0;
+        for (int32_t i = r0; i < r1; ++i)
+          for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int32_t j = col_idx[k];
+            da += (uint64_t)(i > j ? i - j : j - i);
+            dr += (uint64_t)(pos[i] > pos[j] ? pos[i] - pos[j] : pos[j] - pos[i]);
+          }
+        std::lock_guard<std::mutex> lock(mu);
+        d_atom += da;
+        d_rcm += dr;
+      });
+      take = 2 * d_rcm <= d_atom;
     }
     if (take) order.swap(rcm);
   }
@@ -315,25 +444,22 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   // forward: panel i holds the blocks of block row i, ordered by (b_j, j)
   Members M;
   M.mptr.assign(row_ptr, row_ptr + n + 1);
-  M.mcol.assign(col_idx, col_idx + nnzb);
+  M.mcol.resize(nnzb);
   M.mblk.resize(nnzb);
-  std::iota(M.mblk.begin(), M.mblk.end(), int64_t(0));
+  parallel_rows(n, [&](int32_t r0, int32_t r1) {
+    for (int64_t k = row_ptr[r0]; k < row_ptr[r1]; ++k) {
+      M.mcol[k] = col_idx[k];
+      M.mblk[k] = k;
+    }
+  });
   sort_members(n, b, M);
   layout_direction(n, b, plan.off, M, nnzb, &plan.gbase, order, with_columns, plan.fwd);
 
-  // transposed: panel j holds the blocks (i, j) of block column j, ordered by (b_i, i)
-  std::fill(M.mptr.begin(), M.mptr.end(), 0);
-  for (int64_t k = 0; k < nnzb; ++k) M.mptr[col_idx[k] + 1]++;
-  for (int32_t j = 0; j < n; ++j) M.mptr[j + 1] += M.mptr[j];
-  {
-    std::vector<int64_t> fill(M.mptr.begin(), M.mptr.end() - 1);
-    for (int32_t i = 0; i < n; ++i)
-      for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-        const int64_t u = fill[col_idx[k]]++;
-        M.mcol[u] = i;
-        M.mblk[u] = k;
-      }
-  }
+  // transposed: panel j holds the blocks (i, j) of block column j, ordered
+  // by (b_i, i)
+  M.mptr.swap(T.ptr);
+  M.mcol.swap(T.row);
+  M.mblk.swap(T.blk);
   sort_members(n, b, M);
   layout_direction(n, b, plan.off, M, nnzb, nullptr, order, with_columns, plan.tr);
 }

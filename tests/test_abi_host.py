@@ -320,3 +320,71 @@ def test_large_graph_threaded_planner(lib):
     rc = _case(lib, op.b, op.row_ptr, ci, op.nnz)
     assert rc == _lib.VBCSR_EINVAL
     assert ("in row %d" % early) in lib.vbcsr_last_error().decode()
+
+
+def _rcm_reference(n, rp, ci):
+    """Reverse Cuthill-McKee written out from its definition: neighbours of
+    an atom are the other atoms of its row's and its column's blocks (a pair
+    present both ways counts twice, also in the degree), breadth-first search
+    from the unvisited atom of least (degree, index), neighbours visited in
+    (degree, index) order, the sequence reversed."""
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    off = rows != ci
+    deg = np.bincount(rows[off], minlength=n) + np.bincount(ci[off], minlength=n)
+    nbr = [[] for _ in range(n)]
+    for i, j in zip(rows[off].tolist(), ci[off].tolist()):
+        nbr[i].append(j)
+        nbr[j].append(i)
+    for lst in nbr:
+        lst.sort(key=lambda x: (deg[x], x))
+    seen = np.zeros(n, bool)
+    order = []
+    for s0 in sorted(range(n), key=lambda x: (deg[x], x)):
+        if seen[s0]:
+            continue
+        seen[s0] = True
+        head = len(order)
+        order.append(s0)
+        while head < len(order):
+            v = order[head]
+            head += 1
+            for u in nbr[v]:
+                if not seen[u]:
+                    seen[u] = True
+                    order.append(u)
+    return order[::-1]
+
+
+def test_rcm_order_matches_definition(lib):
+    """Above the threading threshold (9,000 atoms), on a non-symmetric graph
+    with unsorted columns, empty rows and some diagonal blocks: the panels of
+    the forward pages follow the reverse Cuthill-McKee order of the
+    definition, and a rerun gives the same layout."""
+    rng = np.random.default_rng(42)
+    n = 9000
+    cnt = rng.integers(0, 12, n)
+    cnt[rng.choice(n, 40, replace=False)] = 0
+    rows = []
+    for i in range(n):
+        c = rng.choice(n, cnt[i], replace=False) if cnt[i] else np.zeros(0, np.int64)
+        if cnt[i] and rng.random() < 0.3 and i not in c:
+            c[0] = i
+        rows.append(rng.permutation(c))
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    ci = np.concatenate(rows).astype(np.int32)
+    b = rng.choice([1, 4, 9, 13], n).astype(np.int32)
+    nval = int(np.sum(b[np.repeat(np.arange(n), np.diff(rp))].astype(np.int64) * b[ci]))
+    fwd = np.zeros(len(ci), np.int64)
+    tr = np.zeros(len(ci), np.int64)
+    rc, *_ = _plan(lib, b, rp, ci, nval, fwd, tr, order="rcm")
+    assert rc == 0
+    ref = _rcm_reference(n, rp, ci)
+    # panel start of every non-empty row = its smallest forward offset
+    blk_rows = np.repeat(np.arange(n), np.diff(rp))
+    start = np.full(n, np.iinfo(np.int64).max)
+    np.minimum.at(start, blk_rows, fwd)
+    got = [i for i in np.argsort(start, kind="stable") if cnt[i] > 0]
+    assert got == [i for i in ref if cnt[i] > 0]
+    fwd2, tr2 = np.zeros_like(fwd), np.zeros_like(tr)
+    _plan(lib, b, rp, ci, nval, fwd2, tr2, order="rcm")
+    assert np.array_equal(fwd, fwd2) and np.array_equal(tr, tr2)
