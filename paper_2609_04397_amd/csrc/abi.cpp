@@ -63,14 +63,19 @@ int dev_alloc(void **p, size_t bytes) {
   return VBCSR_OK;
 }
 
-template <typename T, typename Alloc>
-int upload(T **dst, const std::vector<T, Alloc> &src, hipStream_t s) {
-  int rc = dev_alloc(reinterpret_cast<void **>(dst), sizeof(T) * src.size());
+template <typename T>
+int upload(T **dst, const T *src, size_t count, hipStream_t s) {
+  int rc = dev_alloc(reinterpret_cast<void **>(dst), sizeof(T) * count);
   if (rc) return rc;
-  if (!src.empty())
-    HIP_TRY(hipMemcpyAsync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s),
+  if (count)
+    HIP_TRY(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s),
             "hipMemcpyAsync");
   return VBCSR_OK;
+}
+
+template <typename T, typename Alloc>
+int upload(T **dst, const std::vector<T, Alloc> &src, hipStream_t s) {
+  return upload(dst, src.data(), src.size(), s);
 }
 
 struct DevDir {
@@ -125,11 +130,16 @@ int alloc_into(vbcsr_mat *A, T **p, size_t count) {
   return rc;
 }
 
-template <typename T, typename Alloc>
-int upload_into(vbcsr_mat *A, T **p, const std::vector<T, Alloc> &v, hipStream_t s) {
-  int rc = upload(p, v, s);
+template <typename T>
+int upload_into(vbcsr_mat *A, T **p, const T *src, size_t count, hipStream_t s) {
+  int rc = upload(p, src, count, s);
   if (rc == VBCSR_OK && *p) A->owned.push_back(*p);
   return rc;
+}
+
+template <typename T, typename Alloc>
+int upload_into(vbcsr_mat *A, T **p, const std::vector<T, Alloc> &v, hipStream_t s) {
+  return upload_into(A, p, v.data(), v.size(), s);
 }
 
 void free_all(vbcsr_mat *A) {
@@ -308,15 +318,12 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   std::vector<int32_t> bvec(block_sizes, block_sizes + n_atoms);
   std::vector<int32_t> offv((size_t)n_atoms);
   for (int32_t i = 0; i < n_atoms; ++i) offv[i] = (int32_t)plan.off[i];
-  std::vector<int64_t> rp(row_ptr, row_ptr + n_atoms + 1);
-  std::vector<int32_t> ci(col_idx, col_idx + plan.nnzb);
-  std::vector<int64_t> gb(plan.gbase.begin(), plan.gbase.end() - 1);
   if ((rc = upload_into(A, &A->b, bvec, s))) return bail(rc);
   if ((rc = upload_into(A, &A->off, offv, s))) return bail(rc);
-  if ((rc = upload_into(A, &A->row_ptr, rp, s))) return bail(rc);
-  if ((rc = upload_into(A, &A->col_idx, ci, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->row_ptr, row_ptr, (size_t)n_atoms + 1, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->col_idx, col_idx, (size_t)plan.nnzb, s))) return bail(rc);
   if ((rc = upload_into(A, &A->blk_row, plan.blk_row, s))) return bail(rc);
-  if ((rc = upload_into(A, &A->gbase, gb, s))) return bail(rc);
+  if ((rc = upload_into(A, &A->gbase, plan.gbase.data(), (size_t)plan.nnzb, s))) return bail(rc);
   for (int d = 0; d < 2; ++d) {
     const DirPlan &P = d == 0 ? plan.fwd : plan.tr;
     DevDir &D = A->dir[d];
@@ -881,31 +888,60 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
 
   // final block-norm filter: drop computed blocks whose norm is below eps
   t0 = clk::now();
-  std::vector<int64_t> crp(plan.row_ptr);
-  std::vector<int32_t> ccol(plan.oj.begin(), plan.oj.end());
+  // C's structure: the symbolic pattern, or the filtered one built below
+  std::vector<int64_t> crp;
+  std::vector<int32_t> ccol;
+  const int64_t *c_rp = plan.row_ptr.data();
+  const int32_t *c_ci = plan.oj.data();
+  int64_t c_nnzb = nC;
   const double *final_vals = cvals;
   int64_t final_nvals = nvals;
   if (eps > 0.0 && nC > 0) {
     std::vector<double> nrm;
     if ((rc = d2h(nrm, cnorm, (size_t)nC, s))) return rc;
     HIP_TRY(hipStreamSynchronize(s), "spgemm");
-    std::vector<int64_t> sbase, dbase;
-    std::vector<int32_t> size;
-    ccol.clear();
-    int64_t c = 0, pos = 0;
-    for (int32_t i = 0; i < n; ++i) {
-      crp[i] = (int64_t)ccol.size();
-      for (; c < plan.row_ptr[i + 1]; ++c) {
-        if (nrm[c] < eps) continue;
-        ccol.push_back(plan.oj[c]);
-        sbase.push_back(plan.obase[c]);
-        dbase.push_back(pos);
-        size.push_back((int32_t)(plan.obase[c + 1] - plan.obase[c]));
-        pos += size.back();
+    // kept blocks and values per row, prefixes, then the rows in parallel
+    std::vector<int64_t> vrp((size_t)n + 1, 0);
+    crp.assign((size_t)n + 1, 0);
+    parallel_rows(n, [&](int32_t r0, int32_t r1) {
+      for (int32_t i = r0; i < r1; ++i) {
+        int64_t k = 0, v = 0;
+        for (int64_t c = plan.row_ptr[i]; c < plan.row_ptr[i + 1]; ++c)
+          if (!(nrm[c] < eps)) {
+            ++k;
+            v += plan.obase[c + 1] - plan.obase[c];
+          }
+        crp[i + 1] = k;
+        vrp[i + 1] = v;
       }
+    });
+    for (int32_t i = 0; i < n; ++i) {
+      crp[i + 1] += crp[i];
+      vrp[i + 1] += vrp[i];
     }
-    crp[n] = (int64_t)ccol.size();
-    if ((int64_t)ccol.size() < nC) {
+    const int64_t nk = crp[n];
+    ccol.resize(nk);
+    RawVec<int64_t> sbase(nk), dbase(nk);
+    RawVec<int32_t> size(nk);
+    parallel_rows(n, [&](int32_t r0, int32_t r1) {
+      for (int32_t i = r0; i < r1; ++i) {
+        int64_t u = crp[i], pos = vrp[i];
+        for (int64_t c = plan.row_ptr[i]; c < plan.row_ptr[i + 1]; ++c) {
+          if (nrm[c] < eps) continue;
+          ccol[u] = plan.oj[c];
+          sbase[u] = plan.obase[c];
+          dbase[u] = pos;
+          size[u] = (int32_t)(plan.obase[c + 1] - plan.obase[c]);
+          pos += size[u];
+          ++u;
+        }
+      }
+    });
+    const int64_t pos = vrp[n];
+    c_rp = crp.data();
+    c_ci = ccol.data();
+    c_nnzb = nk;
+    if (nk < nC) {
       double *packed = nullptr;
       int64_t *d_sb = nullptr, *d_db = nullptr;
       int32_t *d_sz = nullptr;
@@ -918,15 +954,15 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
       final_nvals = pos;
     }
   }
-  st.nnzb = (int64_t)ccol.size();
+  st.nnzb = c_nnzb;
   st.ms_filter = ms_since(t0);
 
   // C as an ordinary handle over the same atoms
   t0 = clk::now();
   vbcsr_plan_opts copts{};
   if (opts) copts = *opts;
-  rc = create_impl(out, n, b.data(), crp.data(), ccol.empty() ? nullptr : ccol.data(), final_vals,
-                   true, final_nvals, VBCSR_FP64, &copts, stream);
+  rc = create_impl(out, n, b.data(), c_rp, c_nnzb ? c_ci : nullptr, final_vals, true, final_nvals,
+                   VBCSR_FP64, &copts, stream);
   if (rc) return rc;
   st.ms_build = ms_since(t0);
   if (stats) *stats = st;

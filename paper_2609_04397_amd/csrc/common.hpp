@@ -2,10 +2,13 @@
 // gfx950 kernels of the variable-block sparse library.
 #pragma once
 
+#include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -36,6 +39,27 @@ static_assert(sizeof(RowDesc) == 32, "RowDesc layout");
 // kPageSlack zero values.
 constexpr int64_t kPanelAlign = 4;
 constexpr int64_t kPageSlack = 2;
+
+// Run body(r0, r1) over chunks of 512 rows of [0, n) on up to 16 threads
+// (one thread when n is below 8192).
+template <typename F>
+inline void parallel_rows(int32_t n, F &&body) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < 8192) nt = 1;
+  const int32_t chunk = 512;
+  std::atomic<int32_t> next{0};
+  auto work = [&]() {
+    for (;;) {
+      const int32_t r0 = next.fetch_add(chunk);
+      if (r0 >= n) break;
+      body(r0, std::min(n, r0 + chunk));
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto &x : th) x.join();
+}
 
 // A std::vector whose new elements are left uninitialised: large host
 // buffers are then first written (and paged in) by the threads that fill

@@ -16,26 +16,6 @@
 
 namespace vbcsr {
 
-// Run body(r0, r1) over row chunks on up to 16 threads (one for small n).
-template <typename F>
-static void parallel_rows(int32_t n, F &&body) {
-  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (n < 8192) nt = 1;
-  const int32_t chunk = 512;
-  std::atomic<int32_t> next{0};
-  auto work = [&]() {
-    for (;;) {
-      const int32_t r0 = next.fetch_add(chunk);
-      if (r0 >= n) break;
-      body(r0, std::min(n, r0 + chunk));
-    }
-  };
-  std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
-  work();
-  for (auto &x : th) x.join();
-}
-
 int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                    int64_t n_values, std::string &err) {
   if (n < 0) { err = "n_atoms must be >= 0"; return VBCSR_EINVAL; }

@@ -34,7 +34,7 @@ unsigned worker_count(int32_t n) {
 
 // body(worker, r0, r1) over chunks of rows, nt workers (worker 0 is the caller).
 template <typename F>
-void parallel_rows(int32_t n, unsigned nt, F &&body) {
+void parallel_rows_w(int32_t n, unsigned nt, F &&body) {
   const int32_t chunk = 256;
   std::atomic<int32_t> next{0};
   auto work = [&](unsigned t) {
@@ -68,7 +68,7 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
   // pass 1, one sweep over the products of each row: candidates, their
   // bounds (summed over k in A's stored order, then B's), product counts
   // and sum of b_k; the kept ones are stored ascending in j
-  parallel_rows(n, nw, [&](unsigned t, int32_t r0, int32_t r1) {
+  parallel_rows_w(n, nw, [&](unsigned t, int32_t r0, int32_t r1) {
     RowScratch &w = ws[t];
     for (int32_t i = r0; i < r1; ++i) {
       w.cols.clear();
@@ -134,7 +134,7 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
 
   // pass 2: kept blocks, product ranges, and one more sweep to list the
   // products of the kept blocks in A's stored order of k
-  parallel_rows(n, nw, [&](unsigned t, int32_t r0, int32_t r1) {
+  parallel_rows_w(n, nw, [&](unsigned t, int32_t r0, int32_t r1) {
     RowScratch &w = ws[t];
     std::vector<int64_t> next;
     for (int32_t i = r0; i < r1; ++i) {
