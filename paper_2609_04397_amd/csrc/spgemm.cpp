@@ -18,8 +18,29 @@ struct RowScratch {
   std::vector<int32_t> nprod;  // products of candidate j
   std::vector<int64_t> bksum;  // sum of b_k over the products of candidate j
   std::vector<int32_t> cols;
+  std::vector<uint64_t> bits;  // candidate bitmap over [jmin, jmax]
   explicit RowScratch(int32_t n) : acc(n, 0.0), slot(n, -1), nprod(n, 0), bksum(n, 0) {}
 };
+
+// Put the row's candidates in ascending order: a bitmap scan when the span
+// of their columns is small next to their count (linear in both), else a
+// comparison sort.
+void order_candidates(RowScratch &w, int32_t jmin, int32_t jmax) {
+  const size_t nc = w.cols.size();
+  if (nc < 2) return;
+  const int64_t span = (int64_t)jmax - jmin + 1;
+  if (span > 256 * (int64_t)nc) {
+    std::sort(w.cols.begin(), w.cols.end());
+    return;
+  }
+  const size_t nw = (size_t)((span + 63) >> 6);
+  w.bits.assign(nw, 0);
+  for (int32_t j : w.cols) w.bits[(size_t)(j - jmin) >> 6] |= uint64_t(1) << ((j - jmin) & 63);
+  w.cols.clear();
+  for (size_t q = 0; q < nw; ++q)
+    for (uint64_t v = w.bits[q]; v; v &= v - 1)
+      w.cols.push_back(jmin + (int32_t)(q << 6) + __builtin_ctzll(v));
+}
 
 // The kept blocks of one row, ascending in j, from the counting pass.
 struct RowKept {
@@ -72,6 +93,7 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
     RowScratch &w = ws[t];
     for (int32_t i = r0; i < r1; ++i) {
       w.cols.clear();
+      int32_t jmin = n, jmax = -1;
       for (int64_t ka = arp[i]; ka < arp[i + 1]; ++ka) {
         const int32_t k = aci[ka];
         for (int64_t kb = brp[k]; kb < brp[k + 1]; ++kb) {
@@ -79,13 +101,15 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
           if (w.slot[j] < 0) {
             w.slot[j] = (int32_t)w.cols.size();
             w.cols.push_back(j);
+            jmin = std::min(jmin, j);
+            jmax = std::max(jmax, j);
           }
           if (thr) w.acc[j] += an[ka] * bn[kb];
           ++w.nprod[j];
           w.bksum[j] += b[k];
         }
       }
-      std::sort(w.cols.begin(), w.cols.end());
+      order_candidates(w, jmin, jmax);
       cands[i] = (int64_t)w.cols.size();
       RowKept &r = rk[i];
       int64_t np = 0;
