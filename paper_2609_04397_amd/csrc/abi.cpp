@@ -8,7 +8,11 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
+#include <system_error>
 
 #include "../../include/vbcsr.h"
 #include "common.hpp"
@@ -21,7 +25,11 @@ namespace {
 thread_local std::string g_last_error;
 
 int fail(int code, const std::string &msg) {
-  g_last_error = msg;
+  try {
+    g_last_error = msg;
+  } catch (...) {
+    g_last_error.clear();
+  }
   return code;
 }
 
@@ -29,6 +37,32 @@ int fail(int code, const std::string &msg) {
 
 namespace vbcsr {
 int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+int api_exception(const char *where) {
+  int code = VBCSR_EINVAL;
+  auto note = [&](int c, const char *what) {
+    code = c;
+    try {
+      g_last_error = std::string(where) + ": " + what;
+    } catch (...) {
+      g_last_error.clear();
+    }
+  };
+  try {
+    throw;
+  } catch (const std::bad_alloc &) {
+    note(VBCSR_ENOMEM, "host memory allocation failed");
+  } catch (const std::length_error &) {
+    note(VBCSR_ENOMEM, "host buffer size out of range");
+  } catch (const std::system_error &e) {
+    note(VBCSR_ENOMEM, e.what());
+  } catch (const std::exception &e) {
+    note(VBCSR_EINVAL, e.what());
+  } catch (...) {
+    note(VBCSR_EINVAL, "unknown exception");
+  }
+  return code;
+}
 }  // namespace vbcsr
 
 namespace {
@@ -302,6 +336,16 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   vbcsr_mat *A = new vbcsr_mat();
+  // frees the partial handle on every early return and on an exception
+  struct Guard {
+    vbcsr_mat *&h;
+    ~Guard() {
+      if (h) {
+        free_all(h);
+        delete h;
+      }
+    }
+  } guard{A};
   A->n = n_atoms;
   A->N = plan.N;
   A->nnzb = plan.nnzb;
@@ -310,11 +354,7 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   A->prec = prec;
   if (opts) A->opts = *opts;
 
-  auto bail = [&](int code) {
-    free_all(A);
-    delete A;
-    return code;
-  };
+  auto bail = [&](int code) { return code; };
   std::vector<int32_t> bvec(block_sizes, block_sizes + n_atoms);
   std::vector<int32_t> offv((size_t)n_atoms);
   for (int32_t i = 0; i < n_atoms; ++i) offv[i] = (int32_t)plan.off[i];
@@ -396,6 +436,7 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     if (e != hipSuccess) return bail(hip_fail(e, "create"));
   }
   *out = A;
+  A = nullptr;  // owned by the caller now
   return VBCSR_OK;
 }
 
@@ -443,7 +484,7 @@ const char *vbcsr_last_error(void) { return g_last_error.c_str(); }
 int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *row_ptr,
                     const int32_t *col_idx, int64_t n_values, int32_t *n_shapes, int32_t *shapes,
                     int32_t max_shapes, int64_t *fwd_pos, int64_t *tr_pos, int64_t *page_values,
-                    const vbcsr_plan_opts *opts) {
+                    const vbcsr_plan_opts *opts) try {
   HostPlan plan;
   int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan, false);
   if (rc) return rc;
@@ -455,16 +496,20 @@ int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *
   if (tr_pos) std::copy(plan.tr.blk_pos.begin(), plan.tr.blk_pos.end(), tr_pos);
   if (page_values) *page_values = plan.fwd.n_values;
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_plan_host");
 }
 
 int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
                  const int64_t *row_ptr, const int32_t *col_idx, const double *values,
-                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream) {
+                 int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream) try {
   return create_impl(out, n_atoms, block_sizes, row_ptr, col_idx, values, false, n_values, prec,
                      opts, stream);
+} catch (...) {
+  return api_exception("vbcsr_create");
 }
 
-int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream) {
+int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (dtype != 0 && dtype != 1) return fail(VBCSR_EINVAL, "dtype must be 0 (double) or 1 (float)");
   if (A->nnz == 0) return VBCSR_OK;
@@ -484,26 +529,32 @@ int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype,
   if (rc) return rc;
   if (e != hipSuccess) return hip_fail(e, "set_values");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_set_values");
 }
 
 int vbcsr_spmm(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nrhs,
-               double alpha, double beta, void *stream) {
+               double alpha, double beta, void *stream) try {
   int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
   if (rc || A->N == 0) return rc;
   return product(A, 0, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
                  static_cast<hipStream_t>(stream));
+} catch (...) {
+  return api_exception("vbcsr_spmm");
 }
 
 int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy,
-                 int32_t nrhs, double alpha, double beta, void *stream) {
+                 int32_t nrhs, double alpha, double beta, void *stream) try {
   int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
   if (rc || A->N == 0) return rc;
   return product(A, 1, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
                  static_cast<hipStream_t>(stream));
+} catch (...) {
+  return api_exception("vbcsr_spmm_t");
 }
 
 int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X, int64_t ldx,
-                int32_t nrhs, void *dA, void *stream) {
+                int32_t nrhs, void *dA, void *stream) try {
   int rc = check_vectors(A, dY, lddy, X, ldx, nrhs, false);
   if (rc) return rc;
   if (A->nnz == 0) return VBCSR_OK;
@@ -527,9 +578,11 @@ int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
   }
   if (err != hipSuccess) return hip_fail(err, "sddmm kernel launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_sddmm");
 }
 
-int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes) {
+int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes) try {
   if (!A || !bytes) return fail(VBCSR_EINVAL, "NULL argument");
   if (nrhs <= 0) return fail(VBCSR_EINVAL, "nrhs must be >= 1");
   if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
@@ -538,11 +591,13 @@ int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree,
   // two recurrence vectors, the per-workgroup partial moments, all moments
   *bytes = 2 * vec + 8 * parts * nrhs + 8 * (int64_t)(degree + 1) * nrhs;
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_cheb_workspace_bytes");
 }
 
 int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
                        int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
-                       void *stream) {
+                       void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
@@ -605,11 +660,13 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
   if (e != hipSuccess) return hip_fail(e, "cheb_moments");
   std::copy(mu.begin(), mu.end(), mu_host);
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_cheb_moments");
 }
 
 int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t nrhs,
                                int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
-                               void *stream) {
+                               void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
@@ -690,11 +747,13 @@ int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, i
     }
   }
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_cheb_moments_doubled");
 }
 
 int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev, int64_t ldp,
                     const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
-                    int64_t ws_bytes, void *stream) {
+                    int64_t ws_bytes, void *stream) try {
   int rc = check_vectors(A, Tk, ldt, Tprev, ldp, nrhs, true);
   if (rc) return rc;
   if (nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be <= 4096");
@@ -713,16 +772,20 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
   hipError_t e = launch_reduce_partials(parts, product_workgroups(A->n), nrhs, mu_dev, s);
   if (e != hipSuccess) return hip_fail(e, "moment reduction launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_cheb_step");
 }
 
 int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
-               int32_t *n_shapes) {
+               int32_t *n_shapes) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (n_rows) *n_rows = A->N;
   if (nnzb) *nnzb = A->nnzb;
   if (n_values) *n_values = A->nnz;
   if (n_shapes) *n_shapes = A->n_shapes;
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_info");
 }
 
 void vbcsr_destroy(vbcsr_mat *A) {
@@ -732,7 +795,7 @@ void vbcsr_destroy(vbcsr_mat *A) {
 }
 
 int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_ptr,
-                        int32_t *col_idx) {
+                        int32_t *col_idx) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if ((A->n && (!block_sizes || !row_ptr)) || (A->nnzb && !col_idx))
     return fail(VBCSR_EINVAL, "output pointer is NULL");
@@ -748,9 +811,11 @@ int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_p
     HIP_TRY(hipMemcpy(col_idx, A->col_idx, sizeof(int32_t) * A->nnzb, hipMemcpyDeviceToHost),
             "hipMemcpy");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_get_structure");
 }
 
-int vbcsr_get_values(const vbcsr_mat *A, void *values, int dtype, void *stream) {
+int vbcsr_get_values(const vbcsr_mat *A, void *values, int dtype, void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (A->prec == VBCSR_BF16X3)
     return fail(VBCSR_EUNSUPPORTED, "BF16X3 handles keep only the split pages");
@@ -764,10 +829,12 @@ int vbcsr_get_values(const vbcsr_mat *A, void *values, int dtype, void *stream) 
                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "unpack kernel launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_get_values");
 }
 
 int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double eps,
-                 const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream) {
+                 const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream) try {
   using clk = std::chrono::steady_clock;
   if (!out) return fail(VBCSR_EINVAL, "out is NULL");
   *out = nullptr;
@@ -967,10 +1034,12 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   st.ms_build = ms_since(t0);
   if (stats) *stats = st;
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_spgemm");
 }
 
 int vbcsr_kpm_dos(const double *mu, int32_t n_moments, int32_t damping, const double *x,
-                  int64_t npts, double *rho, double *work, void *stream) {
+                  int64_t npts, double *rho, double *work, void *stream) try {
   if (n_moments < 1) return fail(VBCSR_EINVAL, "n_moments must be >= 1");
   if (damping != VBCSR_KPM_NONE && damping != VBCSR_KPM_JACKSON)
     return fail(VBCSR_EINVAL, "damping must be VBCSR_KPM_NONE or VBCSR_KPM_JACKSON");
@@ -988,18 +1057,22 @@ int vbcsr_kpm_dos(const double *mu, int32_t n_moments, int32_t damping, const do
   // a workspace allocated here is freed on return: finish with it first
   if (!work) HIP_TRY(hipStreamSynchronize(s), "kpm_dos");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_kpm_dos");
 }
 
-int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, double *threshold) {
+int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, double *threshold) try {
   if (n_moments < 1 || n_states < 1 || !(fraction > 0.0) || !threshold)
     return fail(VBCSR_EINVAL, "need n_moments >= 1, n_states >= 1, fraction > 0, threshold");
   const double sigma = M_PI / n_moments;
   *threshold = fraction / ((double)n_states * sigma * std::sqrt(2.0 * M_PI));
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_kpm_threshold");
 }
 
 int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double threshold, double *lo,
-                  double *hi) {
+                  double *hi) try {
   if (!lo || !hi || (npts > 0 && (!x || !rho)) || npts < 0)
     return fail(VBCSR_EINVAL, "array pointer is NULL or npts < 0");
   for (int64_t i = 1; i < npts; ++i)
@@ -1017,6 +1090,8 @@ int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double thres
     prev = i;
   }
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_kpm_gap");
 }
 
 }  // extern "C"

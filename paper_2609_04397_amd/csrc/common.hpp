@@ -5,8 +5,10 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <exception>
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <utility>
@@ -41,24 +43,41 @@ constexpr int64_t kPanelAlign = 4;
 constexpr int64_t kPageSlack = 2;
 
 // Run body(r0, r1) over chunks of 512 rows of [0, n) on up to 16 threads
-// (one thread when n is below 8192).
+// (one thread when n is below 8192).  A thread that cannot be started leaves
+// its share to the others; an exception thrown by body stops the remaining
+// chunks and is rethrown here once every thread has joined.
 template <typename F>
 inline void parallel_rows(int32_t n, F &&body) {
   unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (n < 8192) nt = 1;
-  const int32_t chunk = 512;
-  std::atomic<int32_t> next{0};
+  const int64_t chunk = 512;
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
   auto work = [&]() {
-    for (;;) {
-      const int32_t r0 = next.fetch_add(chunk);
-      if (r0 >= n) break;
-      body(r0, std::min(n, r0 + chunk));
+    try {
+      for (;;) {
+        const int64_t r0 = next.fetch_add(chunk);
+        if (r0 >= n) break;
+        body((int32_t)r0, (int32_t)std::min<int64_t>(n, r0 + chunk));
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (!err) err = std::current_exception();
+      next.store(n);
     }
   };
   std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  for (unsigned t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work);
+    } catch (...) {
+      break;
+    }
+  }
   work();
   for (auto &x : th) x.join();
+  if (err) std::rethrow_exception(err);
 }
 
 // A std::vector whose new elements are left uninitialised: large host
@@ -150,5 +169,10 @@ void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int3
 // Record `msg` as the calling thread's last error (read by vbcsr_last_error)
 // and return `code`.
 int set_error(int code, const std::string &msg);
+
+// For a catch (...) around an entry point: the status of the exception in
+// flight (ENOMEM for host allocation and thread-resource failures, EINVAL
+// otherwise), with `where` and its message recorded as the last error.
+int api_exception(const char *where);
 
 }  // namespace vbcsr

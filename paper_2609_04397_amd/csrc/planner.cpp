@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <mutex>
 #include <numeric>
 #include <thread>
@@ -248,11 +249,32 @@ static void transpose_graph(int32_t n, const int64_t *row_ptr, const int32_t *co
     rb[t] = std::max(rb[t], rb[t - 1]);
   }
   std::vector<int64_t> cnt((size_t)R * n, 0);
+  // ranges whose thread cannot be started run in the caller; an exception
+  // is rethrown once every thread has joined
   auto over_ranges = [&](auto &&body) {
+    std::exception_ptr err;
+    std::mutex mu;
+    auto run = [&](int64_t t) {
+      try {
+        body(t);
+      } catch (...) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (!err) err = std::current_exception();
+      }
+    };
     std::vector<std::thread> th;
-    for (int64_t t = 1; t < R; ++t) th.emplace_back(body, t);
-    body(0);
+    int64_t started = 1;
+    for (; started < R; ++started) {
+      try {
+        th.emplace_back(run, started);
+      } catch (...) {
+        break;
+      }
+    }
+    run(0);
+    for (int64_t t = started; t < R; ++t) run(t);
     for (auto &x : th) x.join();
+    if (err) std::rethrow_exception(err);
   };
   over_ranges([&](int64_t t) {
     int64_t *c = cnt.data() + t * n;

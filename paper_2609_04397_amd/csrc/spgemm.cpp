@@ -3,6 +3,8 @@
 // the kept pattern and the per-block product lists the device consumes.
 #include <algorithm>
 #include <atomic>
+#include <exception>
+#include <mutex>
 #include <thread>
 
 #include "common.hpp"
@@ -53,22 +55,40 @@ unsigned worker_count(int32_t n) {
   return n < 4096 ? 1u : std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
 }
 
-// body(worker, r0, r1) over chunks of rows, nt workers (worker 0 is the caller).
+// body(worker, r0, r1) over chunks of rows, nt workers (worker 0 is the
+// caller).  A worker thread that cannot be started leaves its share to the
+// others; an exception thrown by body stops the remaining chunks and is
+// rethrown here once every thread has joined.
 template <typename F>
 void parallel_rows_w(int32_t n, unsigned nt, F &&body) {
-  const int32_t chunk = 256;
-  std::atomic<int32_t> next{0};
+  const int64_t chunk = 256;
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
   auto work = [&](unsigned t) {
-    for (;;) {
-      const int32_t r0 = next.fetch_add(chunk);
-      if (r0 >= n) break;
-      body(t, r0, std::min(n, r0 + chunk));
+    try {
+      for (;;) {
+        const int64_t r0 = next.fetch_add(chunk);
+        if (r0 >= n) break;
+        body(t, (int32_t)r0, (int32_t)std::min<int64_t>(n, r0 + chunk));
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (!err) err = std::current_exception();
+      next.store(n);
     }
   };
   std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work, t);
+  for (unsigned t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work, t);
+    } catch (...) {
+      break;
+    }
+  }
   work(0);
   for (auto &x : th) x.join();
+  if (err) std::rethrow_exception(err);
 }
 
 }  // namespace

@@ -81,7 +81,7 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
                       const int64_t *row_ptr, const int32_t *col_idx, const int32_t *image,
                       int32_t n_images, const int32_t *shifts, const double *tau,
                       const double *values, int64_t n_values, vbcsr_prec prec,
-                      const vbcsr_plan_opts *opts, void *stream) {
+                      const vbcsr_plan_opts *opts, void *stream) try {
   if (!out) return zfail(VBCSR_EINVAL, "out is NULL");
   *out = nullptr;
   if (prec == VBCSR_BF16X3) return zfail(VBCSR_EUNSUPPORTED, "complex operators are FP64 or FP32");
@@ -208,6 +208,16 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   vbcsr_zmat *Z = new vbcsr_zmat();
+  // frees the partial handle on every early return and on an exception
+  struct Guard {
+    vbcsr_zmat *&h;
+    ~Guard() {
+      if (h) {
+        zfree(h);
+        delete h;
+      }
+    }
+  } guard{Z};
   Z->n = n_atoms;
   Z->n_images = n_images;
   Z->N = plan.N;
@@ -219,11 +229,7 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
   Z->has_tau = tau != nullptr;
   Z->krp_host = krp;
   Z->kci_host = kci;
-  auto bail = [&](int code) {
-    zfree(Z);
-    delete Z;
-    return code;
-  };
+  auto bail = [&](int code) { return code; };
   if ((rc = zup(Z, &Z->b, block_sizes, (size_t)n_atoms, s)) ||
       (rc = zup(Z, &Z->image, cimage.data(), (size_t)nnzb, s)) ||
       (rc = zup(Z, &Z->blk_row, crow.data(), (size_t)nnzb, s)) ||
@@ -262,10 +268,13 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bail(zhip(e, "zmat_create"));
   *out = Z;
+  Z = nullptr;  // owned by the caller now
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_create");
 }
 
-int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *stream) {
+int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *stream) try {
   if (!Z || !k) return zfail(VBCSR_EINVAL, "handle or k is NULL");
   if (!std::isfinite(k[0]) || !std::isfinite(k[1]) || !std::isfinite(k[2]))
     return zfail(VBCSR_EINVAL, "k must be finite");
@@ -301,11 +310,13 @@ int vbcsr_zmat_sample(vbcsr_zmat *Z, const double *k, int32_t convention, void *
   e = launch_zsample(sp, Z->pages[0], Z->pages[1], (int)celem(Z), s);
   if (e != hipSuccess) return zhip(e, "sample kernel launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_sample");
 }
 
 int vbcsr_zmat_spmm(const vbcsr_zmat *Z, const void *X, int64_t ldx, void *Y, int64_t ldy,
                     int32_t nrhs, const double *alpha, const double *beta, int32_t adjoint,
-                    void *stream) {
+                    void *stream) try {
   if (!Z || !alpha || !beta) return zfail(VBCSR_EINVAL, "handle, alpha or beta is NULL");
   if (nrhs <= 0) return zfail(VBCSR_EINVAL, "nrhs must be >= 1");
   if (ldx < nrhs || ldy < nrhs) return zfail(VBCSR_EINVAL, "leading dimension smaller than nrhs");
@@ -331,24 +342,30 @@ int vbcsr_zmat_spmm(const vbcsr_zmat *Z, const void *X, int64_t ldx, void *Y, in
   }
   if (e != hipSuccess) return zhip(e, "complex product kernel launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_spmm");
 }
 
-int vbcsr_zmat_info(const vbcsr_zmat *Z, int64_t *n_rows, int64_t *nnzb_k, int64_t *n_values_k) {
+int vbcsr_zmat_info(const vbcsr_zmat *Z, int64_t *n_rows, int64_t *nnzb_k, int64_t *n_values_k) try {
   if (!Z) return zfail(VBCSR_EINVAL, "handle is NULL");
   if (n_rows) *n_rows = Z->N;
   if (nnzb_k) *nnzb_k = Z->nkb;
   if (n_values_k) *n_values_k = Z->nkv;
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_info");
 }
 
-int vbcsr_zmat_get_structure(const vbcsr_zmat *Z, int64_t *row_ptr, int32_t *col_idx) {
+int vbcsr_zmat_get_structure(const vbcsr_zmat *Z, int64_t *row_ptr, int32_t *col_idx) try {
   if (!Z || !row_ptr || (Z->nkb && !col_idx)) return zfail(VBCSR_EINVAL, "NULL argument");
   std::copy(Z->krp_host.begin(), Z->krp_host.end(), row_ptr);
   std::copy(Z->kci_host.begin(), Z->kci_host.end(), col_idx);
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_get_structure");
 }
 
-int vbcsr_zmat_get_values(const vbcsr_zmat *Z, void *values, void *stream) {
+int vbcsr_zmat_get_values(const vbcsr_zmat *Z, void *values, void *stream) try {
   if (!Z) return zfail(VBCSR_EINVAL, "handle is NULL");
   if (Z->nkv == 0) return VBCSR_OK;
   if (!values) return zfail(VBCSR_EINVAL, "values is NULL");
@@ -356,6 +373,8 @@ int vbcsr_zmat_get_values(const vbcsr_zmat *Z, void *values, void *stream) {
                                 Z->kbase, Z->nkb, values, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return zhip(e, "unpack kernel launch");
   return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_zmat_get_values");
 }
 
 void vbcsr_zmat_destroy(vbcsr_zmat *Z) {

@@ -388,3 +388,46 @@ def test_rcm_order_matches_definition(lib):
     fwd2, tr2 = np.zeros_like(fwd), np.zeros_like(tr)
     _plan(lib, b, rp, ci, nval, fwd2, tr2, order="rcm")
     assert np.array_equal(fwd, fwd2) and np.array_equal(tr, tr2)
+
+
+_OOM_CHILD = r"""
+import ctypes, resource, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2609_04397_amd import _lib
+sys.path.insert(0, sys.argv[1] + "/tests")
+from test_abi_host import _plan
+lib = _lib.load()
+rng = np.random.default_rng(0)
+n, per = 20000, 60
+rp = np.arange(0, n * per + 1, per, dtype=np.int64)
+ci = np.concatenate([np.sort(rng.choice(n, per, replace=False)) for _ in range(n)]).astype(np.int32)
+b = np.full(n, 4, np.int32)
+nval = 16 * n * per
+fwd = np.zeros(n * per, np.int64)
+tr = np.zeros(n * per, np.int64)
+def vm_bytes():
+    for line in open("/proc/self/status"):
+        if line.startswith("VmSize:"):
+            return int(line.split()[1]) * 1024
+soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+resource.setrlimit(resource.RLIMIT_AS, (vm_bytes() + (32 << 20), hard))
+rc, *_ = _plan(lib, b, rp, ci, nval, fwd, tr, order="rcm")
+msg = lib.vbcsr_last_error().decode()
+resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+rc2, *_ = _plan(lib, b, rp, ci, nval, fwd, tr, order="rcm")
+print(rc, rc2, msg)
+"""
+
+
+def test_host_allocation_failure_is_a_status(lib):
+    """With the address space capped just above what the process holds, the
+    threaded planner cannot allocate its tables: the entry point returns
+    VBCSR_ENOMEM with a message naming it (no exception crosses the C ABI),
+    and succeeds again once the cap is lifted."""
+    r = subprocess.run([sys.executable, "-c", _OOM_CHILD, ROOT], capture_output=True, text=True,
+                       timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    rc, rc2, msg = r.stdout.strip().split(" ", 2)
+    assert int(rc) == _lib.VBCSR_ENOMEM and "vbcsr_plan_host" in msg, r.stdout
+    assert int(rc2) == 0
