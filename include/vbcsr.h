@@ -21,6 +21,8 @@
  * (vbcsr_spgemm copies the two handles' block sizes back to compare them,
  * before any kernel runs).
  * Asynchronous device faults are reported as VBCSR_EHIP by a later call.
+ * No C++ exception crosses this interface: a failed host allocation (or a
+ * worker thread that cannot be started) is VBCSR_ENOMEM.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
  * are enqueued asynchronously; the library synchronises the device only in
