@@ -21,8 +21,9 @@
  * (vbcsr_spgemm copies the two handles' block sizes back to compare them,
  * before any kernel runs).
  * Asynchronous device faults are reported as VBCSR_EHIP by a later call.
- * No C++ exception crosses this interface: a failed host allocation (or a
- * worker thread that cannot be started) is VBCSR_ENOMEM.
+ * No C++ exception crosses this interface: a failed host allocation is
+ * VBCSR_ENOMEM, and host worker threads that cannot be started leave their
+ * work to the others.
  *
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
  * are enqueued asynchronously; the library synchronises the device only in
