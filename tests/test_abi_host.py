@@ -411,6 +411,9 @@ def vm_bytes():
         if line.startswith("VmSize:"):
             return int(line.split()[1]) * 1024
 soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+if hard != resource.RLIM_INFINITY:
+    print("skip")
+    sys.exit(0)
 resource.setrlimit(resource.RLIMIT_AS, (vm_bytes() + (32 << 20), hard))
 rc, *_ = _plan(lib, b, rp, ci, nval, fwd, tr, order="rcm")
 msg = lib.vbcsr_last_error().decode()
@@ -428,6 +431,8 @@ def test_host_allocation_failure_is_a_status(lib):
     r = subprocess.run([sys.executable, "-c", _OOM_CHILD, ROOT], capture_output=True, text=True,
                        timeout=300)
     assert r.returncode == 0, r.stderr[-2000:]
+    if r.stdout.strip() == "skip":
+        pytest.skip("the address-space limit of this process cannot be raised back")
     rc, rc2, msg = r.stdout.strip().split(" ", 2)
     assert int(rc) == _lib.VBCSR_ENOMEM and "vbcsr_plan_host" in msg, r.stdout
     assert int(rc2) == 0
