@@ -243,10 +243,16 @@ __global__ void __launch_bounds__(kThreads) k_zspmm_mfma(ZSpmmParams<double> P, 
       v4d rr[NT], ii[NT], ri[NT], ir[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) rr[t] = ii[t] = ri[t] = ir[t] = v4d{0.0, 0.0, 0.0, 0.0};
-      auto ld = [&](int s, double2 &a, double2 (&x)[NT]) {
+      // three stages: the column index of slice s + 2, the values and X rows
+      // of slice s + 1 (whose index arrived one slice earlier), the matrix
+      // instructions of slice s; slices past the end repeat the last one
+      auto ld_idx = [&](int s) {
+        const int k = 4 * s + kq;
+        return k < K ? cx[min(k, K - 1)] : -1;
+      };
+      auto ld = [&](int s, int xr, double2 &a, double2 (&x)[NT]) {
         const int k = 4 * s + kq;
         a = zload(ra, ar < b ? (uint32_t)(k * b + ar) * 16u : kOut);
-        const int xr = k < K ? cx[min(k, K - 1)] : -1;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
           const int c = c0 + t * 16 + m;
@@ -257,10 +263,12 @@ __global__ void __launch_bounds__(kThreads) k_zspmm_mfma(ZSpmmParams<double> P, 
       };
       if (nsl > 0) {
         double2 a, x[NT];
-        ld(0, a, x);
+        int xi1 = ld_idx(min(1, nsl - 1));
+        ld(0, ld_idx(0), a, x);
         for (int s = 0; s < nsl; ++s) {
+          const int xi2 = ld_idx(min(s + 2, nsl - 1));
           double2 an, xn[NT];
-          ld(min(s + 1, nsl - 1), an, xn);
+          ld(min(s + 1, nsl - 1), xi1, an, xn);
 #pragma unroll
           for (int t = 0; t < NT; ++t) {
             rr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, x[t].x, rr[t], 0, 0, 0);
@@ -271,6 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_zspmm_mfma(ZSpmmParams<double> P, 
           a = an;
 #pragma unroll
           for (int t = 0; t < NT; ++t) x[t] = xn[t];
+          xi1 = xi2;
         }
       }
       // accumulator element e of quarter-wave kq: tile row kq + 4e, column m
