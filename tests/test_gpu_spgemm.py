@@ -228,3 +228,30 @@ def test_spgemm_result_planned_in_rcm_order():
     X = torch.randn(op.N, 9, dtype=torch.float64, device="cuda")
     assert torch.equal(C1.spmm(X), C2.spmm(X))
     compare(op, op, 0.0, C2, C2.values().cpu().numpy())
+
+
+def _wide_sparse(seed, n, per, bset, b=None):
+    """``per`` random columns in each of ``n`` rows (ascending): rows of the
+    product have few candidates spread over many atoms."""
+    rng = np.random.default_rng(seed)
+    if b is None:
+        b = rng.choice(np.asarray(bset, np.int32), size=n).astype(np.int32)
+    cols = [np.sort(rng.choice(n, per, replace=False)) for _ in range(n)]
+    row_ptr = np.arange(0, n * per + 1, per, dtype=np.int64)
+    ci = np.concatenate(cols).astype(np.int32)
+    rows = np.repeat(np.arange(n), per)
+    values = rng.uniform(-1.0, 1.0, size=int((b[rows].astype(np.int64) * b[ci]).sum()))
+    return Operator("wide", b, row_ptr, ci, values, np.zeros(ci.shape[0]), {"seed": seed})
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.5])
+def test_spgemm_few_candidates_over_many_atoms(eps):
+    """6,000 atoms with two blocks per row: each row of C has at most four
+    candidates spread over the whole atom range, the case where the symbolic
+    stage orders candidates by sorting rather than by a bitmap scan."""
+    print("case spgemm wide sparse", eps, flush=True)
+    A = _wide_sparse(11, 6000, 2, (1, 4, 9))
+    B = _wide_sparse(12, 6000, 2, (1, 4, 9), b=A.b)
+    Am, Bm, C, st, vals = gpu_product(A, B, eps)
+    compare(A, B, eps, C, vals)
+    assert st["candidates"] <= 4 * 6000
