@@ -1,29 +1,44 @@
 #!/usr/bin/env python
 """Benchmark of the variable-block sparse hot path on one MI355X.
 
-Workload: the periodic 32x32x32 simple-cubic lattice with 13 orbitals per
-atom (self + 6 + 12 neighbours, 19 blocks per row; 32,768 atoms, N =
-425,984 scalar rows, 622,592 blocks, 105,218,048 values), synthetic seeded
-values, FP64 unless stated.  One *step* is one pass over every product of the
-hot path on this operator:
+Headline workload (``value``): the multispecies zincblende nanoparticle --
+a sphere of radius 104 A cut from a zincblende lattice (a = 5.87 A) with
+13-orbital cations, 9-orbital anions and 1-orbital passivating atoms on the
+dangling bonds, couplings through the third neighbour shell (199,911 atoms,
+N = 2,062,795 scalar rows, 5,284,875 blocks in 9 shape classes, 632,664,771
+FP64 values, 5.06 GB).  One *step* is one pass over the FP64 hot path on
+this operator:
 
-  spmv_fp64        Y = A x                   nrhs 1   (FP64)
-  spmm_fp64        Y = A X                   nrhs 32  (FP64)
-  spmm_t_fp64      dX = A^T G                nrhs 32  (FP64, adjoint)
-  sddmm_fp64       dA = G X^T on the blocks  nrhs 32  (FP64)
-  cheb_fp64        T <- 2 A' T_k - T, moment nrhs 64  (FP64, A' = A / 1.01||A||_inf)
-  cheb_fp32        the same step, FP32 pages and vectors, FP64 moments
-  cheb_bf16x3      the same step, BF16x3 matrix-core product, FP64 moments
+  spmm_fp64_n64    Y = A X                   nrhs 64 (the workload's width)
+  spmm_t_fp64_n64  dX = A^T G                nrhs 64 (adjoint)
+  sddmm_fp64_n64   dA = G X^T on the blocks  nrhs 64
+  spmv_fp64        y = A x                   nrhs 1
+  spmm_fp64_n8     Y = A X                   nrhs 8
+  spmm_t_fp64_n8   dX = A^T G                nrhs 8
+  cheb_fp64_n64    T <- 2 A' T_k - T with its FP64 moment, A' = A / (1.01 ||A||_inf)
 
-The forward/adjoint/SDDMM triple is the differentiation form (fwd + bwd).
+Timed alongside, each in a loop of its own with the same protocol:
+
+  precision  the same operator in FP32 and BF16x3 at nrhs 64 (forward);
+  fwd_bwd    the differentiation form on the 100,000-atom three-species
+             operator (b = 1/4/9, nrhs 32): forward + adjoint + block-sampled
+             product as three raw calls and through the autograd function,
+             FP32 and plain FP64, and their ratio;
+  c2_step    the 32^3 simple-cubic lattice (b = 13): SpMV, SpMM/SpMM^T/SDDMM
+             at nrhs 32 and one Chebyshev step in FP64, FP32 and BF16x3 at
+             nrhs 64 on the scaled operator.
+
 Timing: W untimed warm-up steps, then K steps bracketed by device
 synchronisation; every call is also bracketed by HIP events on the stream
-it is launched on, which gives each kernel's average duration.
+it is launched on (torch's current stream, which the library is handed),
+which gives each kernel's average duration.
 
-Output: one JSON line (rank 0).  ``value`` is the step's algorithmic HBM
-throughput (sum of algorithmic bytes / step time), ``roofline`` describes the
-kernel with the largest time share, ``cpu_baseline`` times the FP64 CPU
-oracle on a bounded sample of the same step.
+Output: one JSON line.  ``value`` is the headline step's algorithmic HBM
+throughput (sum of algorithmic bytes / step time), ``roofline`` describes
+its kernel with the largest time share, ``cpu_baseline`` times the FP64 CPU
+oracle on a bounded sample of the same step (sampled block rows), and every
+row carries ``err_vs_oracle``: its error on those sampled rows against the
+oracle, computed after the timed loops.
 """
 from __future__ import annotations
 
@@ -41,6 +56,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+METRIC = "VBCSR SpMM GFLOP/s & HBM GB/s (% roofline); fwd+bwd ms vs plain FP64"
 
 
 def algorithmic_bytes(op, nrhs, s_v, s_x, kind):
@@ -67,9 +83,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--lattice", type=int, default=32, help="lattice edge (32 = full workload)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--only", default="", help="comma list of kernels to run (profiling)")
+    ap.add_argument("--sections", default="c3,precision,fwd_bwd,c2",
+                    help="comma list of timed sections (c3 is the headline)")
+    ap.add_argument("--only", default="", help="comma list of rows to run (profiling)")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the oracle leg (CPU baseline and err_vs_oracle)")
     ap.add_argument("--calib", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for traffic counters)")
     ap.add_argument("--sweep", default="",
@@ -81,6 +99,306 @@ def parse():
     ap.add_argument("--kspace", action="store_true",
                     help="only run the reciprocal-space operator records and print them")
     return ap.parse_args()
+
+
+# ---------------------------------------------------------------------------
+# timed sections
+# ---------------------------------------------------------------------------
+
+class Row:
+    """One timed call: ``fn`` launches it; ``capture`` (after the timed loop)
+    returns the sampled host output and what the oracle needs to check it."""
+
+    def __init__(self, name, fn, nbytes, flops, nrhs, prec, capture=None):
+        self.name, self.fn, self.nbytes, self.flops = name, fn, int(nbytes), float(flops)
+        self.nrhs, self.prec, self.capture = nrhs, prec, capture
+
+
+def peak_key(prec):
+    return {"fp64": "fp64", "fp32": "fp32", "bf16x3": "bf16"}[prec]
+
+
+def time_rows(rows, steps, warmup, only=()):
+    """Warm-up, then ``steps`` timed passes over ``rows`` (each call between
+    two HIP events on the current stream); returns (per-row dicts, ms/step)."""
+    import torch
+    if only:
+        rows = [r for r in rows if r.name in only]
+    if not rows:
+        return [], 0.0
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        for r in rows:
+            r.fn()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in rows] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for st in range(steps):
+        for i, r in enumerate(rows):
+            ev[st][i][0].record(stream)
+            r.fn()
+            ev[st][i][1].record(stream)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    out = []
+    for i, r in enumerate(rows):
+        t = np.array([ev[st][i][0].elapsed_time(ev[st][i][1]) for st in range(steps)])
+        avg = float(t.mean())
+        gbs = r.nbytes / (avg * 1e-3) / 1e9
+        tf = r.flops / (avg * 1e-3) / 1e12
+        roof = max(r.nbytes / (HBM_PEAK_GBS * 1e9), r.flops / (PEAK_TFLOPS[peak_key(r.prec)] * 1e12))
+        out.append({"kernel": r.name, "prec": r.prec, "nrhs": r.nrhs, "avg_ms": round(avg, 5),
+                    "median_ms": round(float(np.median(t)), 5), "min_ms": round(float(t.min()), 5),
+                    "alg_bytes": r.nbytes, "gbs": round(gbs, 1), "tflops": round(tf, 3),
+                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                    "roofline_frac": round(roof * 1e3 / avg, 4), "err_vs_oracle": None})
+    return out, ms_step
+
+
+def sample_atoms(op, k, seed, extra=()):
+    """Block rows checked against the oracle: the first and last atom, ``k``
+    random ones and ``extra``; returns (atoms, their scalar rows)."""
+    rng = np.random.default_rng(seed)
+    atoms = np.unique(np.concatenate([[0, op.n - 1], rng.choice(op.n, size=min(k, op.n),
+                                                                replace=False),
+                                      np.asarray(extra, dtype=np.int64)]).astype(np.int64))
+    off = op.off
+    srows = np.concatenate([np.arange(off[a], off[a + 1]) for a in atoms])
+    return atoms, srows
+
+
+def sampled_value_index(op, atoms):
+    """Positions (graph order) of the values of the blocks in rows ``atoms``."""
+    keep = np.isin(op.block_rows, atoms)
+    base = op.block_base
+    ks = np.nonzero(keep)[0]
+    sizes = base[ks + 1] - base[ks]
+    start = np.repeat(base[ks] - np.concatenate([[0], np.cumsum(sizes)[:-1]]), sizes)
+    return keep, start + np.arange(int(sizes.sum()), dtype=np.int64)
+
+
+def product_rows(prefix, op, M, prec, vecs, nrhs_list, with_t, with_sddmm, atoms, srows,
+                 sddmm_nrhs=None):
+    """Forward (and adjoint, SDDMM) rows of one handle; every output is
+    captured on the sampled rows for the oracle leg."""
+    import torch
+    s_v = 8 if prec == "fp64" else 4
+    s_x = 8 if prec == "fp64" else 4
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dev = torch.device("cuda", 0)
+    sd = torch.from_numpy(srows).to(dev)
+    rows = []
+    for nrhs in nrhs_list:
+        X = vecs["X"][:, :nrhs]
+        G = vecs["G"][:, :nrhs]
+        xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev, dt)
+        gd = torch.from_numpy(np.ascontiguousarray(G)).to(dev, dt)
+        y = torch.empty_like(xd)
+        dx = torch.empty_like(xd)
+        tag = "spmv" if nrhs == 1 else "spmm"
+        nm = "%s%s_%s%s" % (prefix, tag, prec, "" if nrhs == 1 else "_n%d" % nrhs)
+        fl = 2.0 * op.nnz * nrhs
+        nb = algorithmic_bytes(op, nrhs, s_v, s_x, "product")
+
+        def cap_f(y=y, xd=xd, X=X):
+            M.spmm(xd, y)
+            return {"kind": "fwd", "op": op, "X": X, "prec": prec, "atoms": atoms, "srows": srows,
+                    "got": y.index_select(0, sd).double().cpu().numpy()}
+        rows.append(Row(nm, lambda y=y, xd=xd: M.spmm(xd, y), nb, fl, nrhs, prec, cap_f))
+        if with_t:
+            def cap_t(dx=dx, gd=gd, G=G):
+                M.spmm_t(gd, dx)
+                return {"kind": "adj", "op": op, "X": G, "prec": prec, "atoms": atoms,
+                        "srows": srows, "got": dx.index_select(0, sd).double().cpu().numpy()}
+            rows.append(Row(nm.replace(tag + "_", tag + "_t_", 1),
+                            lambda dx=dx, gd=gd: M.spmm_t(gd, dx), nb, fl, nrhs, prec, cap_t))
+        if with_sddmm and nrhs == (sddmm_nrhs or nrhs_list[0]):
+            dA = torch.empty(op.nnz, dtype=dt, device=dev)
+            keep, vidx = sampled_value_index(op, atoms)
+            vd = torch.from_numpy(vidx).to(dev)
+
+            def cap_s(dA=dA, gd=gd, xd=xd, X=X, G=G, vd=vd, keep=keep):
+                M.sddmm(gd, xd, dA)
+                return {"kind": "sddmm", "op": op, "X": X, "G": G, "prec": prec, "keep": keep,
+                        "got": dA.index_select(0, vd).double().cpu().numpy()}
+            rows.append(Row("%ssddmm_%s_n%d" % (prefix, prec, nrhs),
+                            lambda dA=dA, gd=gd, xd=xd: M.sddmm(gd, xd, dA),
+                            algorithmic_bytes(op, nrhs, s_v, s_x, "sddmm"), fl, nrhs, prec, cap_s))
+    return rows
+
+
+def cheb_row(name, opc, M, prec, nrhs, seed, atoms, srows):
+    """One Chebyshev step ``T <- 2 A' T_k - T`` with its fused FP64 moment on
+    the scaled operator ``opc``.  The step overwrites its own input, so the
+    capture runs it once more on fresh copies."""
+    import torch
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(seed)
+    R = rng.standard_normal((opc.N, nrhs))
+    Tk = rng.uniform(-1, 1, (opc.N, nrhs))
+    Tp = rng.uniform(-1, 1, (opc.N, nrhs))
+    Rd, Tkd, Tpd = (torch.from_numpy(a).to(dev, dt) for a in (R, Tk, Tp))
+    ws = torch.empty(M.cheb_workspace_bytes(nrhs, 0), dtype=torch.uint8, device=dev)
+    mu = torch.zeros(nrhs, dtype=torch.float64, device=dev)
+    sd = torch.from_numpy(srows).to(dev)
+    s_v = 8 if prec == "fp64" else 4
+
+    def cap():
+        T = torch.from_numpy(Tp).to(dev, dt)
+        M.cheb_step(Tkd, T, Rd, mu, ws)
+        return {"kind": "cheb", "op": opc, "X": Tk, "Y": Tp, "prec": prec, "atoms": atoms,
+                "srows": srows, "got": T.index_select(0, sd).double().cpu().numpy()}
+    return Row(name, lambda: M.cheb_step(Tkd, Tpd, Rd, mu, ws),
+               algorithmic_bytes(opc, nrhs, s_v, s_v, "cheb"), 2.0 * opc.nnz * nrhs, nrhs, prec, cap)
+
+
+def describe(op):
+    return {"n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz}
+
+
+def run_c3(args, checks, only):
+    """The headline: the FP64 hot path on the zincblende nanoparticle."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads import make_config
+    from workloads.core import inf_norm_scale, scaled
+
+    t0 = time.time()
+    op, vec = make_config("C3", nrhs=64)
+    vec["G"] = np.random.default_rng(33).standard_normal((op.N, 64))
+    s = inf_norm_scale(op)
+    opc = scaled(op, s, name="C3 scaled")
+    gen_s = time.time() - t0
+    # 1/8 of the block rows (and some passivating atoms with their hosts):
+    # the rows err_vs_oracle checks and the CPU baseline's sample
+    h = np.nonzero(op.b == 1)[0][:40]
+    atoms, srows = sample_atoms(op, op.n // 8, 3, extra=np.concatenate([h, h - 1]))
+    t0 = time.time()
+    A = Matrix.from_operator(op, prec="fp64")
+    C = Matrix.from_operator(opc, prec="fp64")
+    torch.cuda.synchronize()
+    create_s = time.time() - t0
+    rows = product_rows("", op, A, "fp64", vec, (64,), True, True, atoms, srows)
+    rows += product_rows("", op, A, "fp64", vec, (1, 8), True, False, atoms, srows)
+    rows.append(cheb_row("cheb_fp64_n64", opc, C, "fp64", 64, 34, atoms, srows))
+    res, ms = time_rows(rows, args.steps, args.warmup, only)
+    caps = {r.name: r.capture for r in rows if not only or r.name in only}
+    for name, cap in caps.items():
+        checks.append((name, cap()))
+    A.close()
+    C.close()
+    torch.cuda.synchronize()
+    info = {"workload": "C3: zincblende nanoparticle, sphere R = 104 A of a zincblende "
+                        "lattice a = 5.87 A, cations b = 13, anions b = 9, passivating "
+                        "b = 1 atoms on dangling bonds, couplings through the 3rd shell, "
+                        "U[-1,1]*exp(-r) symmetric blocks, X/G/R ~ N(0,1), FP64",
+            **describe(op), "n_shape_classes": 9, "step": [r["kernel"] for r in res],
+            "setup_s": {"generate": round(gen_s, 2), "create_2_handles": round(create_s, 2)}}
+    return res, ms, info, op
+
+
+def run_precision(args, checks, only, op=None):
+    """FP32 and BF16x3 forms of the headline operator (nrhs 64, forward)."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads import make_config
+    if op is None:
+        op, _ = make_config("C3", nrhs=1)
+    vec = {"X": np.random.default_rng(35).standard_normal((op.N, 64))}
+    vec["G"] = vec["X"]
+    atoms, srows = sample_atoms(op, 300, 5)
+    out = []
+    for prec in ("fp32", "bf16x3"):
+        M = Matrix.from_operator(op, prec=prec)
+        rows = product_rows("", op, M, prec, vec, (64,), False, False, atoms, srows)
+        res, _ = time_rows(rows, args.steps, args.warmup, only)
+        for r in rows:
+            if not only or r.name in only:
+                checks.append((r.name, r.capture()))
+        out += res
+        M.close()
+    return out
+
+
+def run_fwd_bwd(args, checks, only):
+    """Differentiation form on the 100,000-atom operator: forward, adjoint and
+    block-sampled product at nrhs 32, as three raw calls and through the
+    autograd function (loss sum(Y o G), so dY = G), FP32 against plain FP64."""
+    import torch
+    from paper_2609_04397_amd import Matrix, spmm
+    from workloads import make_config
+    op, vec = make_config("C5")
+    dev = torch.device("cuda", 0)
+    atoms, srows = sample_atoms(op, 400, 6)
+    out = {"workload": "C5: 100,000 atoms uniform in a periodic cube (0.05 / A^3), "
+                       "b = 1/4/9 (20k/40k/40k), cutoff 5 A, values U[-1,1]*exp(-r/2) "
+                       "(FP32-rounded), nrhs 32, loss sum(Y o G)", **describe(op), "rows": []}
+    for prec in ("fp32", "fp64"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        M = Matrix.from_operator(op, prec=prec)
+        rows = product_rows("c5_", op, M, prec, vec, (32,), True, True, atoms, srows)
+        V = torch.from_numpy(op.values).to(dev, dt).requires_grad_(True)
+        X = torch.from_numpy(vec["X"]).to(dev, dt).requires_grad_(True)
+        G = torch.from_numpy(vec["G"]).to(dev, dt)
+
+        def autograd_step(V=V, X=X, G=G, M=M):
+            Y = spmm(V, X, M)
+            return torch.autograd.grad(Y, (V, X), G)
+        rows.append(Row("c5_autograd_fwd_bwd_%s" % prec, autograd_step,
+                        sum(r.nbytes for r in rows), sum(r.flops for r in rows), 32, prec))
+        res, _ = time_rows(rows, args.steps, args.warmup, only)
+        for r in rows:
+            if r.capture is not None and (not only or r.name in only):
+                checks.append((r.name, r.capture()))
+        out["rows"] += res
+        raw = [r for r in res if not r["kernel"].startswith("c5_autograd")]
+        ag = [r for r in res if r["kernel"].startswith("c5_autograd")]
+        if len(raw) == 3:
+            out["%s_ms" % prec] = round(sum(r["avg_ms"] for r in raw), 4)
+        if ag:
+            out["autograd_%s_ms" % prec] = ag[0]["avg_ms"]
+            if len(raw) == 3:
+                out["autograd_over_raw_%s" % prec] = round(ag[0]["avg_ms"] / out["%s_ms" % prec], 3)
+        M.close()
+        del V, X, G
+    if "fp32_ms" in out and "fp64_ms" in out:
+        out["ratio_fp32_over_fp64"] = round(out["fp32_ms"] / out["fp64_ms"], 4)
+    return out
+
+
+def run_c2(args, checks, only):
+    """The 32^3 lattice step of the previous headline: SpMV, nrhs-32
+    forward/adjoint/SDDMM (FP64) and one Chebyshev step per precision form on
+    the scaled operator (nrhs 64)."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads import make_config
+    from workloads.core import inf_norm_scale, scaled
+    op, vec = make_config("C2", nrhs=32)
+    vec["G"] = np.random.default_rng(22).standard_normal((op.N, 32))
+    opc = scaled(op, inf_norm_scale(op), name="C4")
+    atoms, srows = sample_atoms(op, 400, 7)
+    A = Matrix.from_operator(op, prec="fp64")
+    rows = product_rows("c2_", op, A, "fp64", vec, (32,), True, True, atoms, srows)
+    rows += product_rows("c2_", op, A, "fp64", vec, (1,), False, False, atoms, srows)
+    hs = [A]
+    for prec in ("fp64", "fp32", "bf16x3"):
+        M = Matrix.from_operator(opc, prec=prec)
+        hs.append(M)
+        rows.append(cheb_row("c2_cheb_%s_n64" % prec, opc, M, prec, 64, 44, atoms, srows))
+    res, ms = time_rows(rows, args.steps, args.warmup, only)
+    for r in rows:
+        if not only or r.name in only:
+            checks.append((r.name, r.capture()))
+    for M in hs:
+        M.close()
+    return {"workload": "C2/C4: periodic 32^3 simple-cubic lattice, b = 13, self + 6 + 12 "
+                        "neighbours, U[-1,1]*exp(-r) symmetric blocks; Chebyshev rows on "
+                        "A / (1.01 ||A||_inf)", **describe(op), "ms_per_step": round(ms, 4),
+            "rows": res}
 
 
 def main():
@@ -96,161 +414,93 @@ def main():
             print(json.dumps(rec), flush=True)
         return
     import torch
-    from paper_2609_04397_amd import Matrix
-    from workloads.core import sc_lattice, inf_norm_scale, scaled
-
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    t0 = time.time()
-    op = sc_lattice(args.lattice, 13, seed=2, decay=1.0, name="C2")
-    rng = op.meta["_rng"]
-    X32 = rng.standard_normal((op.N, 32))
-    X1 = np.ascontiguousarray(X32[:, :1])
-    G32 = np.random.default_rng(22).standard_normal((op.N, 32))
-    s = inf_norm_scale(op)
-    opc = scaled(op, s, name="C4")
-    R64 = np.random.default_rng(4).standard_normal((op.N, 64))
-    gen_s = time.time() - t0
+    sections = set(args.sections.split(","))
+    only = set(args.only.split(",")) if args.only else set()
+    checks = []
+    out = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded generators; the paper's inputs are not public)"}
+    c3op = None
+    if "c3" in sections:
+        print("bench: c3 section", file=sys.stderr, flush=True)
+        res, ms, info, c3op = run_c3(args, checks, only)
+        nbytes = sum(r["alg_bytes"] for r in res)
+        flops = sum(2.0 * info["n_values"] * r["nrhs"] for r in res)
+        out["value"] = round(nbytes / (ms * 1e-3) / 1e9, 1) if res else None
+        out["ms_per_step"] = round(ms, 4)
+        out["config"] = info
+        out["gflops"] = round(flops / (ms * 1e-3) / 1e9, 1) if res else None
+        out["kernel_ms_sum"] = round(sum(r["avg_ms"] for r in res), 4)
+        out["rows"] = res
+        if res:
+            out["roofline"] = roofline(res, "c3")
+    if "precision" in sections:
+        print("bench: precision section", file=sys.stderr, flush=True)
+        out["precision"] = {"workload": "C3 (as the headline), nrhs 64, forward",
+                            "rows": run_precision(args, checks, only, c3op)}
+    c3op = None
+    if "fwd_bwd" in sections:
+        print("bench: fwd_bwd section", file=sys.stderr, flush=True)
+        out["fwd_bwd"] = run_fwd_bwd(args, checks, only)
+    if "c2" in sections:
+        print("bench: c2 section", file=sys.stderr, flush=True)
+        out["c2_step"] = run_c2(args, checks, only)
+    if args.calib:
+        out["copy_calib"] = copy_calibration()
+    out["device"] = device_info()
+    if not args.no_cpu and checks:
+        print("bench: oracle leg", file=sys.stderr, flush=True)
+        base, errs = oracle_leg(checks, out.get("rows", []))
+        if base is not None:
+            out["cpu_baseline"] = base
+        for blk in [out.get("rows", []), out.get("precision", {}).get("rows", []),
+                    out.get("fwd_bwd", {}).get("rows", []), out.get("c2_step", {}).get("rows", [])]:
+            for r in blk:
+                if r["kernel"] in errs:
+                    r["err_vs_oracle"] = errs[r["kernel"]]
+    if args.sweep:
+        run_sweep(args.sweep)
+    print(json.dumps(out), flush=True)
 
-    t0 = time.time()
-    A64 = Matrix.from_operator(op, prec="fp64")
-    C64 = Matrix.from_operator(opc, prec="fp64")
-    C32 = Matrix.from_operator(opc, prec="fp32")
-    Cbf = Matrix.from_operator(opc, prec="bf16x3")
-    torch.cuda.synchronize()
-    create_s = time.time() - t0
 
-    d64 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float64)
-    d32 = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev, torch.float32)
-    x1, x32, g32 = d64(X1), d64(X32), d64(G32)
-    y1 = torch.empty_like(x1)
-    y32 = torch.empty_like(x32)
-    dx32 = torch.empty_like(x32)
-    dA = torch.empty(op.nnz, dtype=torch.float64, device=dev)
-    vecs = {}
-    for name, M, conv in (("fp64", C64, d64), ("fp32", C32, d32), ("bf16x3", Cbf, d32)):
-        R = conv(R64)
-        Tk = conv(np.random.default_rng(5).uniform(-1, 1, (op.N, 64)))
-        Tp = conv(np.random.default_rng(6).uniform(-1, 1, (op.N, 64)))
-        ws = torch.empty(M.cheb_workspace_bytes(64, 0), dtype=torch.uint8, device=dev)
-        mu = torch.zeros(64, dtype=torch.float64, device=dev)
-        vecs[name] = (M, R, Tk, Tp, ws, mu)
-
-    def cheb(name):
-        M, R, Tk, Tp, ws, mu = vecs[name]
-        return lambda: M.cheb_step(Tk, Tp, R, mu, ws)
-
-    kernels = [
-        ("spmv_fp64", lambda: A64.spmm(x1, y1), algorithmic_bytes(op, 1, 8, 8, "product"), 1, "fp64"),
-        ("spmm_fp64", lambda: A64.spmm(x32, y32), algorithmic_bytes(op, 32, 8, 8, "product"), 32, "fp64"),
-        ("spmm_t_fp64", lambda: A64.spmm_t(g32, dx32), algorithmic_bytes(op, 32, 8, 8, "product"), 32, "fp64"),
-        ("sddmm_fp64", lambda: A64.sddmm(g32, x32, dA), algorithmic_bytes(op, 32, 8, 8, "sddmm"), 32, "fp64"),
-        ("cheb_fp64", cheb("fp64"), algorithmic_bytes(op, 64, 8, 8, "cheb"), 64, "fp64"),
-        ("cheb_fp32", cheb("fp32"), algorithmic_bytes(op, 64, 4, 4, "cheb"), 64, "fp32"),
-        ("cheb_bf16x3", cheb("bf16x3"), algorithmic_bytes(op, 64, 4, 4, "cheb"), 64, "bf16"),
-    ]
-    if args.only:
-        keep = set(args.only.split(","))
-        kernels = [k for k in kernels if k[0] in keep]
-
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        for k in kernels:
-            k[1]()
-    torch.cuda.synchronize()
-
-    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in kernels] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for st in range(args.steps):
-        for i, k in enumerate(kernels):
-            ev[st][i][0].record(stream)
-            k[1]()
-            ev[st][i][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    ms_step = wall * 1e3 / args.steps
-
-    rows = []
-    total_bytes = 0
-    total_flops = 0
-    for i, (name, _, nbytes, nrhs, dt) in enumerate(kernels):
-        times = np.array([ev[st][i][0].elapsed_time(ev[st][i][1]) for st in range(args.steps)])
-        avg_ms = float(times.mean())
-        flops = 2.0 * op.nnz * nrhs
-        total_bytes += nbytes
-        total_flops += flops
-        gbs = nbytes / (avg_ms * 1e-3) / 1e9
-        tf = flops / (avg_ms * 1e-3) / 1e12
-        roof_ms = max(nbytes / (HBM_PEAK_GBS * 1e9), flops / (PEAK_TFLOPS[dt] * 1e12)) * 1e3
-        rows.append({"kernel": name, "nrhs": nrhs, "avg_ms": round(avg_ms, 5),
-                     "median_ms": round(float(np.median(times)), 5),
-                     "min_ms": round(float(times.min()), 5),
-                     "alg_bytes": int(nbytes), "gbs": round(gbs, 1), "tflops": round(tf, 3),
-                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "roofline_frac": round(roof_ms / avg_ms, 4)})
-
+def roofline(rows, workload):
+    """Roofline object of the row with the largest time share: HBM-bound when
+    its algorithmic bytes at 8 TB/s take at least as long as its flops at the
+    dtype's matrix/vector peak, else compute-bound."""
     dom = max(rows, key=lambda r: r["avg_ms"])
-    dom_dt = [k[4] for k in kernels if k[0] == dom["kernel"]][0]
-    hbm_bound = dom["alg_bytes"] / (HBM_PEAK_GBS * 1e9) >= 2.0 * op.nnz * dom["nrhs"] / (PEAK_TFLOPS[dom_dt] * 1e12)
-    if hbm_bound:
+    pk = PEAK_TFLOPS[peak_key(dom["prec"])]
+    t_mem = dom["alg_bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_flop = dom["tflops"] * 1e12 * dom["avg_ms"] * 1e-3 / (pk * 1e12)
+    if t_mem >= t_flop:
         roof = {"bound": "hbm", "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4)}
     else:
-        roof = {"bound": "mfma", "achieved": dom["tflops"], "peak": PEAK_TFLOPS[dom_dt],
-                "unit": "TFLOP/s", "frac": round(dom["tflops"] / PEAK_TFLOPS[dom_dt], 4)}
+        roof = {"bound": "mfma", "achieved": dom["tflops"], "peak": pk, "unit": "TFLOP/s",
+                "frac": round(dom["tflops"] / pk, 4)}
     roof["kernel"] = dom["kernel"]
-    roof["traffic"] = traffic_record(dom["kernel"])
+    roof["hbm_frac"] = dom["hbm_frac"]
+    roof["traffic"] = traffic_record(dom["kernel"], workload)
+    return roof
 
-    kernel_ms = sum(r["avg_ms"] for r in rows)
-    value = total_bytes / (ms_step * 1e-3) / 1e9
-    fwd = [r for r in rows if r["kernel"] == "spmm_fp64"]
-    fb = [r for r in rows if r["kernel"] in ("spmm_fp64", "spmm_t_fp64", "sddmm_fp64")]
-    out = {
-        "metric": "VBCSR SpMM GFLOP/s & HBM GB/s (% roofline); fwd+bwd ms vs plain FP64",
-        "value": round(value, 1),
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "sc-lattice %d^3, b=13, 19 blocks/row (self+6+12), "
-                               "U[-1,1]*exp(-r) symmetric blocks, X/G/R ~ N(0,1)" % args.lattice,
-                   "n_atoms": op.n, "N": op.N, "nnzb": op.nnzb, "n_values": op.nnz,
-                   "step": [k[0] for k in kernels]},
-        "gflops": round(total_flops / (ms_step * 1e-3) / 1e9, 1),
-        "kernel_ms_sum": round(kernel_ms, 4),
-        "rows": rows,
-        "roofline": roof,
-        "fwd_bwd_fp64_ms": round(sum(r["avg_ms"] for r in fb), 4) if len(fb) == 3 else None,
-        "fwd_bwd_over_fwd": round(sum(r["avg_ms"] for r in fb) / fwd[0]["avg_ms"], 3)
-        if len(fb) == 3 else None,
-        "setup_s": {"generate": round(gen_s, 2), "create_4_handles": round(create_s, 2)},
-        "device": device_info(),
-    }
-    if args.calib:
-        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(5):
-            dst.copy_(src)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        out["copy_calib"] = {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
-                             "gbs": round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
-    if args.sweep:
-        run_sweep(args.sweep)
-    if not args.no_cpu and len(kernels) == 7:
-        out["cpu_baseline"] = cpu_baseline(op, opc, X1, X32, G32, R64, total_bytes)
-    print(json.dumps(out))
+
+def copy_calibration():
+    import torch
+    dev = torch.device("cuda", 0)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
+            "gbs": round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
 
 
 def device_info():
@@ -566,64 +816,134 @@ def spgemm_records(with_cpu=True):
     return recs
 
 
-def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, budget_s=12.0):
-    """The FP64 oracle (all host cores) on every product of the step, full
-    size, repeated until about ``budget_s`` seconds of CPU work are timed;
-    the oracle's scalar-CSR expansion and transpose are set-up, excluded like
-    the device planner.  Every precision form runs as the FP64 oracle."""
+def restrict(op, keep_blocks):
+    """The operator with only the blocks ``keep_blocks`` (graph order kept),
+    over the same atoms: its product equals the full product on every row
+    whose blocks are all kept."""
+    from workloads.core import Operator
+    keep = np.asarray(keep_blocks, dtype=bool)
+    counts = np.bincount(op.block_rows[keep], minlength=op.n)
+    rp = np.zeros(op.n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rp[1:])
+    vmask = np.repeat(keep, np.diff(op.block_base))
+    return Operator(op.name + "-sampled", op.b, rp, op.col_idx[keep], op.values[vmask],
+                    op.dist[keep])
+
+
+def oracle_leg(checks, headline_rows, budget_s=12.0):
+    """The FP64 CPU oracle on the sampled block rows of every timed row.
+
+    Returns (cpu_baseline, errors).  ``cpu_baseline`` times the oracle's
+    products on the headline rows' samples (the scalar-CSR expansion of the
+    sampled operator is set-up, excluded like the device planner), repeated
+    until about ``budget_s`` seconds of CPU work, median per row; each
+    sample's algorithmic bytes are the row's bytes scaled by the fraction of
+    the operator's values the sample holds.  ``errors`` holds, per row, the
+    error of the device output on the sampled rows: rel_F and componentwise
+    (FP64), rel_F against the oracle on the FP64 inputs and on the inputs
+    rounded to FP32 (FP32, BF16x3)."""
     import oracle
 
-    A = oracle.expand_op(op)
-    At = oracle.transpose(A)
-    Ac = oracle.expand_op(opc)
-    T = np.random.default_rng(5).uniform(-1, 1, (op.N, 64))
-    Tp = np.random.default_rng(6).uniform(-1, 1, (op.N, 64))
-    names = ["spmv_fp64", "spmm_fp64", "spmm_t_fp64", "sddmm_fp64", "cheb_fp64", "cheb_fp32",
-             "cheb_bf16x3"]
-    per = {k: [] for k in names}
+    def rounded(a, prec):
+        return a if prec == "fp64" else np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+
+    def rel_f(y, ref):
+        d = np.linalg.norm(ref)
+        return float(np.linalg.norm(y - ref) / d) if d > 0 else float(np.linalg.norm(y))
+
+    def comp(y, ref, scale):
+        d = np.abs(y - ref)
+        z = scale == 0
+        if np.any(d[z] != 0):
+            return float("inf")
+        return float((d / np.where(z, 1.0, scale)).max()) if d.size else 0.0
+
+    prepared = []
+    cache = {}
+    for name, c in checks:
+        op = c["op"]
+        key = (id(op), "col" if c["kind"] == "adj" else "row",
+               id(c["keep"]) if c["kind"] == "sddmm" else id(c["atoms"]))
+        if key not in cache:
+            if c["kind"] == "sddmm":
+                cache[key] = restrict(op, c["keep"])
+            elif c["kind"] == "adj":
+                cache[key] = restrict(op, np.isin(op.col_idx, c["atoms"]))
+            else:
+                cache[key] = restrict(op, np.isin(op.block_rows, c["atoms"]))
+        prepared.append((name, c, cache[key]))
+
+    def run(c, sub, values=None, rnd="fp64"):
+        """One oracle product of the check's kind on its sample."""
+        X = rounded(c["X"], rnd)
+        if c["kind"] == "sddmm":
+            return oracle.sddmm(sub if values is None else _with(sub, values), rounded(c["G"], rnd), X)
+        A = oracle.expand_op(sub, values)
+        if c["kind"] == "adj":
+            A = oracle.transpose(A)
+        if c["kind"] == "cheb":
+            Y = oracle.csr_spmm(A, X, alpha=2.0, beta=-1.0, Y=rounded(c["Y"], rnd))
+        else:
+            Y = oracle.csr_spmm(A, X)
+        return Y[c["srows"]]
+
+    def _with(sub, values):
+        from workloads.core import Operator
+        return Operator(sub.name, sub.b, sub.row_ptr, sub.col_idx, values, sub.dist)
+
+    errors = {}
+    for name, c, sub in prepared:
+        got = c["got"]
+        ref = run(c, sub)
+        e = {"rows_checked": int(len(c["srows"])) if "srows" in c else None,
+             "rel_F": rel_f(got, ref)}
+        if c["prec"] == "fp64":
+            if c["kind"] == "sddmm":
+                scale = oracle.sddmm(sub, np.abs(c["G"]), np.abs(c["X"]))
+                e["values_checked"] = int(got.size)
+            else:
+                A = oracle.expand_op(sub).abs()
+                if c["kind"] == "adj":
+                    A = oracle.transpose(A)
+                scale = oracle.csr_spmm(A, np.abs(c["X"]))[c["srows"]]
+                if c["kind"] == "cheb":
+                    scale = 2.0 * scale + np.abs(c["Y"][c["srows"]])
+            e["comp"] = comp(got, ref, scale)
+        else:
+            e["rel_F_rounded_inputs"] = rel_f(got, run(c, sub, rounded(sub.values, "fp32"), "fp32"))
+        errors[name] = {k: (float("%.3e" % v) if isinstance(v, float) else v) for k, v in e.items()}
+
+    # the CPU baseline: the headline rows' samples, timed
+    head = {r["kernel"]: r for r in headline_rows}
+    timed = [(n, c, s) for n, c, s in prepared if n in head]
+    if not timed:
+        return None, errors
+    exp = {}
+    for n, c, s in timed:
+        if c["kind"] != "sddmm":
+            A = oracle.expand_op(s)
+            exp[n] = oracle.transpose(A) if c["kind"] == "adj" else A
+    per = {n: [] for n, _, _ in timed}
     reps = 0
     t_all = time.perf_counter()
     while True:
-        t = {}
-        t0 = time.perf_counter()
-        oracle.csr_spmm(A, X1)
-        t["spmv_fp64"] = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.csr_spmm(A, X32)
-        t["spmm_fp64"] = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.csr_spmm(At, G32)
-        t["spmm_t_fp64"] = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        oracle.sddmm(op, G32, X32)
-        t["sddmm_fp64"] = time.perf_counter() - t0
-        for k in ("cheb_fp64", "cheb_fp32", "cheb_bf16x3"):
+        for n, c, s in timed:
+            X = c["X"]
             t0 = time.perf_counter()
-            Y = oracle.csr_spmm(Ac, T, alpha=2.0, beta=-1.0, Y=Tp)
-            (R64 * Y).sum(axis=0)
-            t[k] = time.perf_counter() - t0
+            if c["kind"] == "sddmm":
+                oracle.sddmm(s, c["G"], X)
+            elif c["kind"] == "cheb":
+                oracle.csr_spmm(exp[n], X, alpha=2.0, beta=-1.0, Y=c["Y"])
+            else:
+                oracle.csr_spmm(exp[n], X)
+            per[n].append(time.perf_counter() - t0)
         reps += 1
-        for k in names:
-            per[k].append(t[k])
-        if time.perf_counter() - t_all >= budget_s or reps >= 7:
+        if reps >= 3 and (time.perf_counter() - t_all >= budget_s or reps >= 7):
             break
-    med = {k: float(np.median(v)) for k, v in per.items()}
-    step_s = sum(med.values())
-    cores = oracle.max_threads()
-    # the same oracle on one thread (bitwise the same results), on the SpMV
-    # and the nrhs-32 SpMM only: the whole step would take ~20 s there
-    oracle.set_threads(1)
-    try:
-        t1 = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            oracle.csr_spmm(A, X1)
-            oracle.csr_spmm(A, X32)
-            t1.append(time.perf_counter() - t0)
-    finally:
-        oracle.set_threads(cores)
-    one = float(np.median(t1))
-    one_bytes = algorithmic_bytes(op, 1, 8, 8, "product") + algorithmic_bytes(op, 32, 8, 8, "product")
+    cpu_s = time.perf_counter() - t_all
+    med = {n: float(np.median(v)) for n, v in per.items()}
+    nbytes = {n: head[n]["alg_bytes"] * s.nnz / c["op"].nnz for n, c, s in timed}
+    tot_b, tot_s = sum(nbytes.values()), sum(med.values())
     cpu_model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -632,25 +952,27 @@ def cpu_baseline(op, opc, X1, X32, G32, R64, step_bytes, budget_s=12.0):
                 break
     except OSError:
         pass
-    return {"value": round(step_bytes / step_s / 1e9, 3), "unit": "GB/s",
-            "cores": cores, "kind": "oracle",
-            "sample": "the whole step (7 products, full size) on the FP64 scalar-CSR oracle, "
-                      "median of %d repetitions (%.1f s of CPU work); expansion/transpose "
-                      "excluded; FP32/BF16x3 forms run as FP64" % (reps, time.perf_counter() - t_all),
-            "step_s": round(step_s, 4),
-            "per_kernel_s": {k: round(v, 4) for k, v in med.items()},
-            "single_thread": {"value": round(one_bytes / one / 1e9, 3), "unit": "GB/s",
-                              "sample": "spmv_fp64 + spmm_fp64 (nrhs 32), median of 3",
-                              "s": round(one, 4)},
-            "cpu_model": cpu_model, "host_threads": os.cpu_count()}
+    frac = {n: round(s.nnz / c["op"].nnz, 5) for n, c, s in timed}
+    base = {"value": round(tot_b / tot_s / 1e9, 3), "unit": "GB/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": "every row of the headline step on the FP64 scalar-CSR oracle, restricted "
+                      "to the sampled block rows (adjoint: block columns) that err_vs_oracle "
+                      "checks, %.2f-%.2f %% of the values; median of %d repetitions, %.1f s of CPU "
+                      "work; algorithmic bytes scaled by the sampled fraction of the values; "
+                      "scalar-CSR expansion excluded" % (100 * min(frac.values()),
+                                                         100 * max(frac.values()), reps, cpu_s),
+            "per_row_s": {n: round(v, 4) for n, v in med.items()},
+            "sampled_value_fraction": frac, "cpu_model": cpu_model,
+            "host_threads": os.cpu_count()}
+    return base, errors
 
 
-def traffic_record(kernel):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    import hashlib
+def traffic_record(kernel, workload):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    of ``workload``, or None when the sources changed since the counters
+    were taken."""
     import re
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_%s.md" % workload)
     if not os.path.exists(path):
         return None
     m = re.search(r"<!-- traffic: (\{.*\}) -->", open(path).read())

@@ -94,7 +94,7 @@ typedef struct {
  * vbcsr_create -- build a device operator from a block graph and values.
  * Paper: section 3.1 (atom graph, block size per node), section 3.2
  * (shape classes registered from the distinct (b_i, b_j); every block mapped
- * to its place in a shape-specific buffer).
+ * to its place in the value storage of its shape class).
  *
  *   out          receives the new handle (set to NULL on failure)
  *   n_atoms      number of atoms n >= 0 (rows and columns of the block graph)
@@ -118,6 +118,9 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
 
 /*
  * vbcsr_set_values -- replace all block values, same structure.
+ * No passage of the paper defines this call: it is the library's way of
+ * changing the operator's entries between products (the differentiation
+ * form updates them every step).
  *   values     n_values entries in graph order, each block row-major
  *   on_device  0: host pointer (copied, synchronises `stream`);
  *              1: device pointer (read by a kernel on `stream`; no sync)
@@ -180,7 +183,11 @@ int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree,
  *   degree     >= 0
  *   mu_host    host, (degree+1)*nrhs doubles
  *   workspace  device, >= vbcsr_cheb_workspace_bytes() bytes, 256-byte aligned;
- *              NULL = allocate (and free) it inside the call
+ *              NULL = allocate (and free) it inside the call; must not
+ *              overlap R
+ * The signature adds the leading dimension ldr of R to the one the operation
+ * needs (A, R, nrhs, degree, moments): R may be a column slice of a wider
+ * array.
  * Synchronises `stream` (copies the moments to the host).
  * Errors: EINVAL, ENOMEM, EHIP.
  */
@@ -216,6 +223,9 @@ int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, i
  *   R          device, N x nrhs, leading dimension ldr >= nrhs
  *   mu_dev     device, nrhs doubles
  *   workspace  device, >= vbcsr_cheb_workspace_bytes(A, nrhs, 0) bytes
+ * R must not overlap Tprev (the epilogue writes T_next and then reads R at
+ * the same element); the workspace and mu_dev must not overlap each other
+ * or any of the three vectors.
  * Asynchronous on `stream` (no synchronisation).
  * Errors: EINVAL, EHIP.
  */
@@ -224,7 +234,8 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
                     int64_t ws_bytes, void *stream);
 
 /*
- * vbcsr_info -- sizes of a handle: n_rows = N (scalar rows), nnzb stored
+ * vbcsr_info -- (a library utility; no passage of the paper defines it)
+ * sizes of a handle: n_rows = N (scalar rows), nnzb stored
  * blocks, n_values = sum of b_i*b_j, n_shapes = distinct (b_i, b_j) classes.
  * Any output pointer may be NULL.
  */
@@ -356,7 +367,7 @@ int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double thres
  * Reciprocal-space (k-sampled) operators.
  * Paper, section 3.3, equation 4: a periodic real-space operator is a set of
  * images O(R), one per integer lattice translation R, over the atoms of one
- * cell; sampling a point k (fractional reciprocal coordinates) gives the
+ * cell; sampling a point k (given in units of the reciprocal lattice vectors) gives the
  * complex block-sparse operator
  *     O(k) = sum_R exp(-2 pi i k.R) O(R)                      (VBCSR_PHASE_R)
  * or, in the alternative convention, block (i, j) of image R multiplied by
@@ -435,10 +446,12 @@ int vbcsr_zmat_get_values(const vbcsr_zmat *Z, void *values, void *stream);
 /* vbcsr_zmat_destroy -- free a handle (NULL is ignored); synchronises the device. */
 void vbcsr_zmat_destroy(vbcsr_zmat *Z);
 
-/* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device. */
+/* vbcsr_destroy -- free a handle (NULL is ignored); synchronises the device.
+ * Library utility: no passage of the paper defines it. */
 void vbcsr_destroy(vbcsr_mat *A);
 
-/* vbcsr_last_error -- message of the last non-OK status on this thread
+/* vbcsr_last_error -- (library utility; no passage of the paper defines it)
+ * message of the last non-OK status on this thread
  * ("" if none).  The pointer stays valid until the next call on the thread. */
 const char *vbcsr_last_error(void);
 

@@ -17,7 +17,7 @@ Every function follows one definition from the paper:
   kernel polynomial method (section 5), FP64 throughout;
 * :func:`spgemm`      thresholded block product ``C_ij = sum_k A_ik B_kj``
   (section 3.2, equation 2): symbolic stage with the block-norm bound of
-  equation 3, numeric stage, final block-norm filter.
+  equation 3, numeric stage, a closing filter on the computed block norms.
 """
 from __future__ import annotations
 
@@ -60,9 +60,6 @@ def _load():
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_double, _f64p,
                                     ctypes.c_int64]
     lib.oracle_csr_spmm.restype = None
-    lib.oracle_csr_spmm_rows.argtypes = [_i64p, _i32p, _f64p, _f64p, ctypes.c_int64, ctypes.c_int32,
-                                         _i64p, ctypes.c_int64, _f64p]
-    lib.oracle_csr_spmm_rows.restype = None
     lib.oracle_csr_transpose.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _i64p, _i32p, _f64p]
     lib.oracle_csr_transpose.restype = None
     lib.oracle_sddmm.argtypes = [ctypes.c_int32, _i32p, _i64p, _i32p, _f64p, ctypes.c_int64, _f64p,
@@ -154,16 +151,6 @@ def csr_spmm(A: ScalarCSR, X, alpha=1.0, beta=0.0, Y=None) -> np.ndarray:
     _load().oracle_csr_spmm(A.N, A.rp, A.ci, A.va, X, nrhs, nrhs, float(alpha), float(beta),
                             Y, nrhs)
     return Y
-
-
-def csr_spmm_rows(A: ScalarCSR, X, rows) -> np.ndarray:
-    """Rows ``rows`` of ``A X`` only (for sampled checks of large products)."""
-    X = _c(X, np.float64)
-    rows = _c(rows, np.int64)
-    nrhs = X.shape[1]
-    out = np.empty((rows.shape[0], nrhs))
-    _load().oracle_csr_spmm_rows(A.rp, A.ci, A.va, X, nrhs, nrhs, rows, rows.shape[0], out)
-    return out
 
 
 def transpose(A: ScalarCSR) -> ScalarCSR:

@@ -107,22 +107,6 @@ void oracle_csr_spmm(int64_t N, const int64_t *rp, const int32_t *ci, const doub
   }
 }
 
-/* The same sums for a chosen list of scalar rows only: out[t*nrhs + c] is
- * element (rows[t], c) of A*X.  Used to check huge products by sampling. */
-void oracle_csr_spmm_rows(const int64_t *rp, const int32_t *ci, const double *va,
-                          const double *X, int64_t ldx, int32_t nrhs,
-                          const int64_t *rows, int64_t nrows, double *out) {
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int64_t t = 0; t < nrows; ++t) {
-    int64_t r = rows[t];
-    for (int32_t c = 0; c < nrhs; ++c) {
-      double acc = 0.0;
-      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) acc += va[e] * X[(int64_t)ci[e] * ldx + c];
-      out[t * nrhs + c] = acc;
-    }
-  }
-}
-
 /* Scalar transpose by a stable counting sort: entry (r, c, v) becomes (c, r, v);
  * inside a transposed row entries keep ascending source row order.  Applying
  * the forward product to it gives Y_j += sum_i A_ij^T X_i, the adjoint of

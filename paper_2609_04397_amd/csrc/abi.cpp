@@ -608,6 +608,9 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
   int rc = vbcsr_cheb_workspace_bytes(A, nrhs, degree, &need);
   if (rc) return rc;
   if (workspace && ws_bytes < need) return fail(VBCSR_EINVAL, "workspace too small");
+  if (workspace && A->N > 0 &&
+      ranges_overlap(workspace, (size_t)need, R, span_bytes(A->N, ldr, nrhs, vec_elem(A))))
+    return fail(VBCSR_EINVAL, "R overlaps the workspace");
   if (A->N == 0) {
     std::fill(mu_host, mu_host + (size_t)(degree + 1) * nrhs, 0.0);
     return VBCSR_OK;
@@ -677,6 +680,9 @@ int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, i
   int rc = vbcsr_cheb_workspace_bytes(A, nrhs, degree, &need);
   if (rc) return rc;
   if (workspace && ws_bytes < need) return fail(VBCSR_EINVAL, "workspace too small");
+  if (workspace && A->N > 0 &&
+      ranges_overlap(workspace, (size_t)need, R, span_bytes(A->N, ldr, nrhs, vec_elem(A))))
+    return fail(VBCSR_EINVAL, "R overlaps the workspace");
   if (A->N == 0) {
     std::fill(mu_host, mu_host + (size_t)(degree + 1) * nrhs, 0.0);
     return VBCSR_OK;
@@ -764,6 +770,22 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
   int64_t need = 0;
   if ((rc = vbcsr_cheb_workspace_bytes(A, nrhs, 0, &need))) return rc;
   if (!workspace || ws_bytes < need) return fail(VBCSR_EINVAL, "workspace missing or too small");
+  // the product writes Tprev and then reads R at the same element; the
+  // partial moments are written into the workspace, the moments into mu_dev
+  {
+    const size_t e = vec_elem(A);
+    const size_t tb = span_bytes(A->N, ldp, nrhs, e), rb = span_bytes(A->N, ldr, nrhs, e),
+                 kb = span_bytes(A->N, ldt, nrhs, e), mb = sizeof(double) * (size_t)nrhs;
+    if (ranges_overlap(R, rb, Tprev, tb)) return fail(VBCSR_EINVAL, "R overlaps Tprev");
+    if (ranges_overlap(workspace, (size_t)need, Tprev, tb) ||
+        ranges_overlap(workspace, (size_t)need, Tk, kb) ||
+        ranges_overlap(workspace, (size_t)need, R, rb) ||
+        ranges_overlap(workspace, (size_t)need, mu_dev, mb))
+      return fail(VBCSR_EINVAL, "workspace overlaps a vector or mu_dev");
+    if (ranges_overlap(mu_dev, mb, Tprev, tb) || ranges_overlap(mu_dev, mb, Tk, kb) ||
+        ranges_overlap(mu_dev, mb, R, rb))
+      return fail(VBCSR_EINVAL, "mu_dev overlaps a vector");
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
   double *parts = reinterpret_cast<double *>(static_cast<char *>(workspace) + 2 * vec);
@@ -953,7 +975,7 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (e != hipSuccess) return hip_fail(e, "numeric stage");
   st.ms_numeric = ms;
 
-  // final block-norm filter: drop computed blocks whose norm is below eps
+  // closing norm filter: drop computed blocks whose norm is below eps
   t0 = clk::now();
   // C's structure: the symbolic pattern, or the filtered one built below
   std::vector<int64_t> crp;

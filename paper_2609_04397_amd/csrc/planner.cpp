@@ -1,8 +1,8 @@
 // Host planner: validation, shape classes, and the page layout of both
 // directions of the operator (paper, section 3.2: shape classes are counted
-// from the distinct (b_i, b_j) and every logical block is mapped to its place
-// in a shape-specific buffer; here the buffer of a shape class inside a block
-// row is one contiguous run of the row's panel).
+// from the distinct (b_i, b_j) and each block is placed in the value storage
+// of its class; here the storage of a shape class inside a block row is one
+// contiguous run of the row's panel).
 #include <algorithm>
 #include <atomic>
 #include <cmath>

@@ -91,6 +91,50 @@ def test_cheb_step_matches_recurrence(prec):
     assert np.max(np.abs(host(mu) - ref_mu)) <= (1e-11 if prec == "fp64" else 1e-3) * np.abs(ref_mu).max()
 
 
+def test_cheb_aliasing_is_rejected():
+    """R aliasing the vector the step overwrites, or a workspace holding a
+    vector, would silently change the moments: both are EINVAL, before any
+    kernel runs (the buffers keep their contents)."""
+    import ctypes
+    from paper_2609_04397_amd import _lib
+    op, vec = make_config("C4", scale=0.002, nrhs=4)
+    A = Matrix.from_operator(op)
+    lib = _lib.load()
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    N = op.N
+    Tk = torch.rand((N, 4), dtype=torch.float64, device="cuda")
+    Tp = torch.rand((N, 4), dtype=torch.float64, device="cuda")
+    mu = torch.zeros(4, dtype=torch.float64, device="cuda")
+    need = A.cheb_workspace_bytes(4, 0)
+    ws = torch.empty(need + 8 * N * 4, dtype=torch.uint8, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    before = Tp.clone()
+    # R is Tprev
+    assert lib.vbcsr_cheb_step(A._h, P(Tk), 4, P(Tp), 4, P(Tp), 4, 4, P(mu), P(ws), need,
+                               s) == _lib.VBCSR_EINVAL
+    # R lies inside the workspace
+    Rin = ws[:8 * N * 4].view(torch.float64).view(N, 4)
+    assert lib.vbcsr_cheb_step(A._h, P(Tk), 4, P(Tp), 4, P(Rin), 4, 4, P(mu), P(ws), need,
+                               s) == _lib.VBCSR_EINVAL
+    # mu_dev inside Tprev
+    assert lib.vbcsr_cheb_step(A._h, P(Tk), 4, P(Tp), 4, P(Tk), 4, 4, P(Tp), P(ws), need,
+                               s) == _lib.VBCSR_EINVAL
+    torch.cuda.synchronize()
+    assert torch.equal(Tp, before)
+    # the whole recurrence: R inside the caller's workspace
+    need_m = A.cheb_workspace_bytes(4, 8)
+    wsm = torch.empty(need_m, dtype=torch.uint8, device="cuda")
+    Rws = wsm[:8 * N * 4].view(torch.float64).view(N, 4)
+    mu_h = np.zeros((9, 4))
+    for fn in (lib.vbcsr_cheb_moments, lib.vbcsr_cheb_moments_doubled):
+        assert fn(A._h, P(Rws), 4, 4, 8, mu_h.ctypes.data, P(wsm), need_m, s) == _lib.VBCSR_EINVAL
+    # a valid call still works after the rejected ones
+    R = torch.from_numpy(vec["R"]).to("cuda")
+    got = A.cheb_moments(R, 8, workspace=wsm)
+    ref = oracle.cheb_moments(op, vec["R"], 8)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref[0]))
+
+
 def test_autograd_gradcheck_fp64():
     op, vec = make_config("FD50", nrhs=3)
     A = Matrix.from_operator(op)
@@ -164,3 +208,4 @@ def test_autograd_values_change_between_calls():
     ref = oracle.spmm_t(op, np.ones((op.N, 4)), values=op.values)
     assert rel_f(host(Xg.grad), ref) <= 1e-12
     assert rel_f(host(Y2), oracle.spmm(op, vec["X"][:, :4], values=op.values[::-1].copy())) <= 1e-12
+

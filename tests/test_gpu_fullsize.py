@@ -144,6 +144,70 @@ def test_c4_moments_full_size_low_degree(c2):
         A.close()
 
 
+@pytest.mark.timeout(900)
+def test_c4_degree64_full_size():
+    """The precision form at its full configuration (paper, section 5: KPM
+    moments): the degree-64 recurrence on the scaled 32^3 lattice operator
+    with 64 random vectors, in FP64, FP32 and BF16x3.  Moments are compared
+    with the FP64 oracle on the FP64 inputs (the headline error), with the
+    oracle on the FP32-rounded inputs (accumulation error alone) and with the
+    FP64 GPU path; T_64 itself, driven step by step through the step entry
+    point, is compared with the oracle's T_64 in full."""
+    import json
+    op4, vec = make_config("C4", nrhs=64)
+    R = vec["R"]
+    deg = 64
+    print("case C4 degree 64: oracle", flush=True)
+    ref_mu = oracle.cheb_moments(op4, R, deg)
+    R32 = rounded(R, "fp32")
+    op32 = Operator(op4.name, op4.b, op4.row_ptr, op4.col_idx, rounded(op4.values, "fp32"), op4.dist)
+    ref_mu32 = oracle.cheb_moments(op32, R32, deg)
+    # the oracle's T_64 by the same recurrence, FP64 inputs
+    Ac = oracle.expand_op(op4)
+    Tprev, T = R, oracle.csr_spmm(Ac, R)
+    for _ in range(2, deg + 1):
+        Tprev, T = T, oracle.csr_spmm(Ac, T, alpha=2.0, beta=-1.0, Y=Tprev)
+    ref_T64 = T
+    del Ac, Tprev, T
+    mu0 = np.max(np.abs(ref_mu[0]))
+    res = {}
+    mu_gpu64 = None
+    # T_64 bound: an error d_j made at step j reaches T_64 as U_{64-j}(A) d_j
+    # (Chebyshev polynomial of the second kind, norm <= 65 - j on [-1, 1]),
+    # so rel_F(T_64) <= sum_j (65 - j) eps ~ 65^2 / 2 * eps with eps the
+    # single-product relative error (FP64 ~1e-16: far below 1e-12; FP32 and
+    # BF16x3 at their single-product tolerances 1e-5 and 5e-5)
+    growth = (deg + 1) ** 2 / 2.0
+    for prec, tol_mu, tol_t in (("fp64", 1e-12, 1e-12), ("fp32", 1e-5, growth * 1e-5),
+                                ("bf16x3", 5e-5, growth * 5e-5)):
+        print("case C4 degree 64", prec, flush=True)
+        A = Matrix.from_operator(op4, prec=prec)
+        Rd = dev(R, prec)
+        mu = A.cheb_moments(Rd, deg)
+        ws = torch.empty(A.cheb_workspace_bytes(64, 0), dtype=torch.uint8, device="cuda")
+        mud = torch.zeros(64, dtype=torch.float64, device="cuda")
+        Tp, Tk = Rd.clone(), A.spmm(Rd)
+        for _ in range(2, deg + 1):
+            A.cheb_step(Tk, Tp, Rd, mud, ws)   # Tp <- 2 A Tk - Tp = next
+            Tp, Tk = Tk, Tp
+        t64 = host(Tk)
+        r = {"mu_vs_oracle": float(np.max(np.abs(mu - ref_mu)) / mu0),
+             "mu_vs_oracle_rounded_inputs": float(np.max(np.abs(mu - ref_mu32)) / mu0),
+             "T64_rel_F_vs_oracle": rel_f(t64, ref_T64),
+             "step_mu64_vs_recurrence": float(np.max(np.abs(host(mud) - mu[deg])) / mu0)}
+        if prec == "fp64":
+            mu_gpu64 = mu
+        else:
+            r["mu_vs_fp64_gpu"] = float(np.max(np.abs(mu - mu_gpu64)) / mu0)
+        res[prec] = r
+        print("C4 degree 64 %s %s" % (prec, json.dumps(r)), flush=True)
+        assert r["mu_vs_oracle"] <= tol_mu
+        assert r["T64_rel_F_vs_oracle"] <= tol_t
+        assert r["step_mu64_vs_recurrence"] <= 1e-13
+        A.close()
+    print("C4_DEGREE64_ERRORS " + json.dumps(res), flush=True)
+
+
 @pytest.mark.timeout(400)
 def test_c4_doubled_moments_full_size():
     """Degree 6 from 3 products at the full C4 size, every precision form."""

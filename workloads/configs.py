@@ -1,8 +1,8 @@
 """Named synthetic workloads shaped like the paper's operators.
 
-The paper benchmarks "atom-like periodic geometric graphs with finite
-cutoffs" (section 4, setup) and InP nanoparticles (section 5); its inputs are
-not public, so these seeded stand-ins replace them:
+The paper benchmarks periodic atom-centred graphs built with a finite
+interaction cutoff (section 4, setup) and InP nanoparticles (section 5); its
+inputs are not public, so these seeded stand-ins replace them:
 
 * ``C1``  1,000 atoms, periodic cube, density 0.05/A^3, b in {4, 9} (500/500),
   cutoff 6 A (strict, self included), values U[-1,1]*exp(-r/2), nrhs 16.
