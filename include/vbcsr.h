@@ -233,6 +233,30 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
                     const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
                     int64_t ws_bytes, void *stream);
 
+/* Size of the device scratch behind vbcsr_cheb_step_noalloc, per GPU. */
+#define VBCSR_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/*
+ * vbcsr_cheb_step_noalloc -- vbcsr_cheb_step without any device allocation
+ * and without a workspace argument, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving or solver loops, harnesses that
+ * forbid hipMalloc.  Same operation, arguments (minus the workspace), results
+ * (bitwise) and errors as vbcsr_cheb_step.
+ * The per-workgroup partial moments go to a scratch array inside the
+ * library: one VBCSR_NOALLOC_SCRATCH_BYTES array per GPU, held from the
+ * library's load until the process ends.  The call needs
+ * 8 * ceil(n_atoms / 4) * nrhs bytes of it and fails with
+ * VBCSR_EUNSUPPORTED beyond that (e.g. n_atoms = 199,911 allows nrhs <= 83).
+ * Every call on one GPU shares that GPU's scratch, which keeps the last
+ * call's partials: calls that overlap in time on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  Nothing in the
+ * scratch needs clearing between calls (each call writes all the partials
+ * it reads).  No hipMalloc, hipFree or allocating routine is called.
+ */
+int vbcsr_cheb_step_noalloc(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev,
+                            int64_t ldp, const void *R, int64_t ldr, int32_t nrhs, double *mu_dev,
+                            void *stream);
+
 /*
  * vbcsr_info -- (a library utility; no passage of the paper defines it)
  * sizes of a handle: n_rows = N (scalar rows), nnzb stored

@@ -18,6 +18,7 @@ VBCSR_EDUP = -3
 VBCSR_ENOMEM = -4
 VBCSR_EHIP = -5
 VBCSR_EUNSUPPORTED = -6
+NOALLOC_SCRATCH_BYTES = 32 << 20  # VBCSR_NOALLOC_SCRATCH_BYTES
 CODE_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EDUP", -4: "ENOMEM", -5: "EHIP",
               -6: "EUNSUPPORTED"}
 
@@ -59,6 +60,7 @@ SIGNATURES = {
     "vbcsr_cheb_moments": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),
     "vbcsr_cheb_moments_doubled": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),
     "vbcsr_cheb_step": (_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i32, _p, _p, _i64, _p]),
+    "vbcsr_cheb_step_noalloc": (_int, [_p, _p, _i64, _p, _i64, _p, _i64, _i32, _p, _p]),
     "vbcsr_info": (_int, [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                           ctypes.POINTER(_i32)]),
     "vbcsr_plan_host": (_int, [_i32, _p, _p, _p, _i64, ctypes.POINTER(_i32), _p, _i32, _p, _p,

@@ -798,6 +798,50 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
   return api_exception("vbcsr_cheb_step");
 }
 
+int vbcsr_cheb_step_noalloc(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev,
+                            int64_t ldp, const void *R, int64_t ldr, int32_t nrhs, double *mu_dev,
+                            void *stream) try {
+  int rc = check_vectors(A, Tk, ldt, Tprev, ldp, nrhs, true);
+  if (rc) return rc;
+  if (nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be <= 4096");
+  if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
+  if (!mu_dev) return fail(VBCSR_EINVAL, "mu_dev is NULL");
+  if (A->N == 0) return VBCSR_OK;
+  if (!R) return fail(VBCSR_EINVAL, "R is NULL");
+  {
+    const size_t e = vec_elem(A);
+    const size_t tb = span_bytes(A->N, ldp, nrhs, e), rb = span_bytes(A->N, ldr, nrhs, e),
+                 kb = span_bytes(A->N, ldt, nrhs, e), mb = sizeof(double) * (size_t)nrhs;
+    if (ranges_overlap(R, rb, Tprev, tb)) return fail(VBCSR_EINVAL, "R overlaps Tprev");
+    if (ranges_overlap(mu_dev, mb, Tprev, tb) || ranges_overlap(mu_dev, mb, Tk, kb) ||
+        ranges_overlap(mu_dev, mb, R, rb))
+      return fail(VBCSR_EINVAL, "mu_dev overlaps a vector");
+  }
+  // the per-workgroup partial moments live in the library's static scratch
+  const int64_t npw = product_workgroups(A->n);
+  const int64_t need = (int64_t)sizeof(double) * npw * nrhs;
+  if (need > (int64_t)kNoAllocScratchBytes)
+    return fail(VBCSR_EUNSUPPORTED,
+                "vbcsr_cheb_step_noalloc: " + std::to_string(need) +
+                    " bytes of partial moments (ceil(n_atoms / 4) * nrhs doubles) exceed the " +
+                    std::to_string(kNoAllocScratchBytes) + "-byte scratch");
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  hipError_t e = noalloc_scratch(&ptr, &bytes);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double *parts = static_cast<double *>(ptr);
+  // every workgroup of the product writes all nrhs of its partials, so the
+  // scratch needs no clearing
+  rc = product(A, 0, Tk, ldt, Tprev, ldp, Tprev, ldp, nrhs, 2.0, -1.0, R, ldr, parts, s);
+  if (rc) return rc;
+  e = launch_reduce_partials(parts, npw, nrhs, mu_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "moment reduction launch");
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_cheb_step_noalloc");
+}
+
 int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
                int32_t *n_shapes) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");

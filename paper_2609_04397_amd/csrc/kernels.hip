@@ -19,6 +19,7 @@
 //
 // Every output element has exactly one writer (no atomics), so results are
 // bitwise reproducible run to run.
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -1670,6 +1671,37 @@ hipError_t launch_columns(const ColumnParams &p, hipStream_t s) {
   hipLaunchKernelGGL(k_columns, dim3((unsigned)((p.nnzb + kThreads - 1) / kThreads)), dim3(kThreads),
                      0, s, p);
   return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------------------
+// scratch of the allocation-free entry points
+// ---------------------------------------------------------------------------
+// One copy per GPU, resident from the module's load to the end of the
+// process.  In host code `scratch` names only the host-side stand-in of the
+// array: its device address is looked up below, once per device, and only
+// that address is ever passed to kernels.
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+hipError_t noalloc_scratch(void **ptr, size_t *bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void *addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = kNoAllocScratchBytes;
+  return hipSuccess;
 }
 
 }  // namespace vbcsr

@@ -157,4 +157,10 @@ struct ColumnParams {
 };
 hipError_t launch_columns(const ColumnParams &p, hipStream_t s);
 
+// Scratch of the allocation-free entry points: a file-scope device array of
+// kNoAllocScratchBytes per GPU.  *ptr receives its address on the current
+// device (looked up with hipGetSymbolAddress on the first call per device).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+hipError_t noalloc_scratch(void **ptr, size_t *bytes);
+
 }  // namespace vbcsr
