@@ -117,6 +117,50 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
                  int64_t n_values, vbcsr_prec prec, const vbcsr_plan_opts *opts, void *stream);
 
 /*
+ * vbcsr_create_local -- the rank-local operator of a distributed block graph.
+ * Paper: section 3.1 (each rank owns a set of atoms and stores their block
+ * rows; the columns they reference are owned atoms or ghosts, the ghosts
+ * ordered by owner rank and then by global id) and section 3.2 (the forward
+ * product first fetches the ghost rows of X; the adjoint returns the
+ * contributions of ghost columns to their owners).
+ *
+ * Local atom ids: 0 .. n_owned-1 are the owned atoms (block rows),
+ * n_owned .. n_owned+n_ghost-1 the ghosts (columns only).  Scalar offsets
+ * run over all local atoms, so N_rows = off_{n_owned} (owned scalar rows)
+ * and N = off_{n_owned+n_ghost} (owned + ghost scalar rows).
+ *   block_sizes  host [n_owned + n_ghost]
+ *   row_ptr      host [n_owned + 1]
+ *   col_idx      host, local column ids in [0, n_owned + n_ghost)
+ *   values, n_values, prec, opts, stream as vbcsr_create
+ * Products on such a handle (A is N_rows x N):
+ *   vbcsr_spmm    X: N x nrhs (owned rows, then the ghost rows received from
+ *                 their owners), Y: N_rows x nrhs;
+ *   vbcsr_spmm_t  X: N_rows x nrhs, Y: N x nrhs -- rows below N_rows are the
+ *                 owned atoms' results, the rest the ghost columns'
+ *                 contributions, to be returned to their owners and added
+ *                 there (vbcsr_halo_pack / vbcsr_halo_reduce);
+ *   vbcsr_sddmm   dY: N_rows x nrhs, X: N x nrhs.
+ * The Chebyshev helpers and vbcsr_spgemm need square operators and return
+ * VBCSR_EUNSUPPORTED for a rank-local one.  vbcsr_info reports n_rows =
+ * N_rows; vbcsr_get_structure returns n_owned + 1 row pointers and
+ * n_owned + n_ghost block sizes; vbcsr_shape gives both dimensions.
+ * Errors: as vbcsr_create (every column id is checked against
+ * n_owned + n_ghost).
+ */
+int vbcsr_create_local(vbcsr_mat **out, int32_t n_owned, int32_t n_ghost,
+                       const int32_t *block_sizes, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *values, int64_t n_values, vbcsr_prec prec,
+                       const vbcsr_plan_opts *opts, void *stream);
+
+/*
+ * vbcsr_shape -- (library utility) the handle's dimensions: block rows and
+ * block columns (atoms), scalar rows N_rows and scalar columns N.  Square
+ * handles have equal pairs.  Any output may be NULL.
+ */
+int vbcsr_shape(const vbcsr_mat *A, int32_t *n_row_atoms, int32_t *n_col_atoms, int64_t *n_rows,
+                int64_t *n_cols);
+
+/*
  * vbcsr_set_values -- replace all block values, same structure.
  * No passage of the paper defines this call: it is the library's way of
  * changing the operator's entries between products (the differentiation
@@ -259,7 +303,8 @@ int vbcsr_cheb_step_noalloc(const vbcsr_mat *A, const void *Tk, int64_t ldt, voi
 
 /*
  * vbcsr_info -- (a library utility; no passage of the paper defines it)
- * sizes of a handle: n_rows = N (scalar rows), nnzb stored
+ * sizes of a handle: n_rows = N_rows (scalar rows of a forward product's
+ * output: N for a square handle), nnzb stored
  * blocks, n_values = sum of b_i*b_j, n_shapes = distinct (b_i, b_j) classes.
  * Any output pointer may be NULL.
  */
@@ -285,8 +330,9 @@ int vbcsr_plan_host(int32_t n_atoms, const int32_t *block_sizes, const int64_t *
 
 /*
  * vbcsr_get_structure -- copy the block graph of a handle to the host.
- *   block_sizes  out [n_atoms]; row_ptr out [n_atoms+1]; col_idx out [nnzb]
- *   (sizes from vbcsr_info; n_atoms = number of block rows).  Synchronous.
+ *   block_sizes  out [n_col_atoms]; row_ptr out [n_row_atoms+1]; col_idx out
+ *   [nnzb] (sizes from vbcsr_shape and vbcsr_info; both atom counts are
+ *   n_atoms for a square handle).  Synchronous.
  * Errors: EINVAL (null handle or output), EHIP.
  */
 int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_ptr,
@@ -386,6 +432,98 @@ int vbcsr_kpm_threshold(int32_t n_moments, int64_t n_states, double fraction, do
  */
 int vbcsr_kpm_gap(const double *x, const double *rho, int64_t npts, double threshold, double *lo,
                   double *hi);
+
+/* ---------------------------------------------------------------------------
+ * Halo exchange of rank-local operators (paper, sections 3.1 and 3.2).
+ * A halo plan describes one rank's share of a distributed block graph: its
+ * owned atoms (ascending global id), its ghosts (ordered by owner rank, then
+ * global id), the local graph for vbcsr_create_local, and the exchange
+ * lists.  Every list is in local scalar rows:
+ *   send buffer  rows send_ptr[s] .. send_ptr[s+1] go to rank s: the scalar
+ *                rows of the owned atoms that rank s's rows reference, in
+ *                ascending global id -- exactly the order of rank s's ghost
+ *                rows from this rank, so a received segment is copied
+ *                unchanged into the ghost rows;
+ *   receive      the ghost rows from owner s are local scalar rows
+ *                N_rows + recv_ptr[s] .. N_rows + recv_ptr[s+1];
+ *   adjoint      the ghost rows of a vbcsr_spmm_t result are returned the
+ *                same way (owner s receives rows N_rows + recv_ptr[s] ..),
+ *                arriving in the layout of this rank's send buffer; the
+ *                reduction map lists, per owned scalar row red_rows[u], the
+ *                buffer rows red_pos[red_ptr[u] .. red_ptr[u+1]) (ascending,
+ *                i.e. rank order) that add into it.
+ * The plan is computed on the host from the whole graph (here every rank's
+ * share lives in one process); the transport between ranks is the
+ * caller's (device copies on one GPU, or point-to-point messages).
+ * ------------------------------------------------------------------------- */
+typedef struct vbcsr_halo vbcsr_halo; /* opaque, host-side, owned by the library */
+
+/*
+ * vbcsr_halo_create -- the plan of rank `rank` of `n_ranks`.
+ *   n_global, block_sizes, row_ptr, col_idx  the global block graph (as
+ *            vbcsr_create takes it; values are not needed)
+ *   owner    host [n_global], owning rank of every atom, in [0, n_ranks)
+ * Host only.  Errors: EINVAL, EDUP, EUNSUPPORTED (as vbcsr_create's
+ * validation), ENOMEM.
+ */
+int vbcsr_halo_create(vbcsr_halo **out, int32_t n_global, const int32_t *block_sizes,
+                      const int64_t *row_ptr, const int32_t *col_idx, const int32_t *owner,
+                      int32_t rank, int32_t n_ranks);
+
+/* vbcsr_halo_info -- sizes: owned and ghost atoms, local blocks and values,
+ * rows of the send buffer, rows of the reduction map.  Outputs may be NULL. */
+int vbcsr_halo_info(const vbcsr_halo *H, int32_t *n_owned, int32_t *n_ghost, int64_t *nnzb,
+                    int64_t *n_values, int64_t *n_send_rows, int64_t *n_red_rows);
+
+/* vbcsr_halo_graph -- the local graph: gid [n_owned+n_ghost] global id of
+ * every local atom, block_sizes [n_owned+n_ghost], row_ptr [n_owned+1],
+ * col_idx [nnzb] (local ids; each row keeps the global order of its blocks).
+ * Outputs may be NULL. */
+int vbcsr_halo_graph(const vbcsr_halo *H, int32_t *gid, int32_t *block_sizes, int64_t *row_ptr,
+                     int32_t *col_idx);
+
+/* vbcsr_halo_local_values -- the owned rows' block values (local graph
+ * order) from the global graph-order values; host arrays. */
+int vbcsr_halo_local_values(const vbcsr_halo *H, const double *global_values, double *local_values);
+
+/* vbcsr_halo_lists -- send_ptr [n_ranks+1], send_rows [n_send_rows],
+ * recv_ptr [n_ranks+1], red_rows [n_red_rows], red_ptr [n_red_rows+1],
+ * red_pos [n_send_rows] (host arrays, any may be NULL); see above. */
+int vbcsr_halo_lists(const vbcsr_halo *H, int64_t *send_ptr, int32_t *send_rows, int64_t *recv_ptr,
+                     int32_t *red_rows, int64_t *red_ptr, int64_t *red_pos);
+
+/* vbcsr_halo_destroy -- free a plan (NULL is ignored). */
+void vbcsr_halo_destroy(vbcsr_halo *H);
+
+/*
+ * vbcsr_halo_pack -- fill a send buffer on the device:
+ *   buf[t*ldb + c] = X[rows[t]*ldx + c],  t < nrows, c < nrhs
+ *   X     device, x_rows x nrhs (leading dimension ldx)
+ *   rows  device [nrows] scalar rows of X (e.g. the send rows); a row outside
+ *         [0, x_rows) is skipped (its buffer row is not written)
+ *   dtype 0 = double, 1 = float;  buf device, nrows x nrhs (ldb), must not
+ *         overlap X
+ * Asynchronous on `stream`.  Errors: EINVAL, EHIP.
+ */
+int vbcsr_halo_pack(const void *X, int64_t x_rows, int64_t ldx, const int32_t *rows,
+                    int64_t nrows, int32_t nrhs, int32_t dtype, void *buf, int64_t ldb,
+                    void *stream);
+
+/*
+ * vbcsr_halo_reduce -- add returned adjoint contributions to their rows:
+ *   Y[red_rows[u]*ldy + c] += sum over e in [red_ptr[u], red_ptr[u+1]) of
+ *                             buf[red_pos[e]*ldb + c]
+ * summed in e order, one writer per element (no atomics; bitwise
+ * reproducible).  red_rows must be distinct (the plan's are).
+ *   Y         device, y_rows x nrhs (ldy);  buf device, buf_rows x nrhs (ldb)
+ *   red_rows, red_ptr, red_pos  device arrays (the plan's reduction map);
+ *             indices outside Y or the buffer are skipped
+ * Asynchronous on `stream`.  Errors: EINVAL, EHIP.
+ */
+int vbcsr_halo_reduce(void *Y, int64_t y_rows, int64_t ldy, const int32_t *red_rows,
+                      const int64_t *red_ptr, const int64_t *red_pos, int64_t n_red,
+                      const void *buf, int64_t buf_rows, int64_t ldb, int32_t nrhs, int32_t dtype,
+                      void *stream);
 
 /* ---------------------------------------------------------------------------
  * Reciprocal-space (k-sampled) operators.

@@ -4,13 +4,16 @@
 the package itself touches neither.
 """
 
-__all__ = ["Matrix", "spmm", "VbcsrError"]
+__all__ = ["Matrix", "spmm", "Halo", "VbcsrError"]
 
 
 def __getattr__(name):
     if name in ("Matrix", "spmm"):
         from . import matrix
         return getattr(matrix, name)
+    if name == "Halo":
+        from .halo import Halo
+        return Halo
     if name == "VbcsrError":
         from ._lib import VbcsrError
         return VbcsrError

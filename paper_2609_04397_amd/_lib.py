@@ -52,6 +52,19 @@ class SpgemmStats(ctypes.Structure):
 SIGNATURES = {
     "vbcsr_create": (_int, [ctypes.POINTER(_p), _i32, _p, _p, _p, _p, _i64, _int,
                             ctypes.POINTER(PlanOpts), _p]),
+    "vbcsr_create_local": (_int, [ctypes.POINTER(_p), _i32, _i32, _p, _p, _p, _p, _i64, _int,
+                                  ctypes.POINTER(PlanOpts), _p]),
+    "vbcsr_shape": (_int, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                           ctypes.POINTER(_i64)]),
+    "vbcsr_halo_create": (_int, [ctypes.POINTER(_p), _i32, _p, _p, _p, _p, _i32, _i32]),
+    "vbcsr_halo_info": (_int, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                               ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "vbcsr_halo_graph": (_int, [_p, _p, _p, _p, _p]),
+    "vbcsr_halo_local_values": (_int, [_p, _p, _p]),
+    "vbcsr_halo_lists": (_int, [_p, _p, _p, _p, _p, _p, _p]),
+    "vbcsr_halo_destroy": (None, [_p]),
+    "vbcsr_halo_pack": (_int, [_p, _i64, _i64, _p, _i64, _i32, _i32, _p, _i64, _p]),
+    "vbcsr_halo_reduce": (_int, [_p, _i64, _i64, _p, _p, _p, _i64, _p, _i64, _i64, _i32, _i32, _p]),
     "vbcsr_set_values": (_int, [_p, _p, _int, _int, _p]),
     "vbcsr_spmm": (_int, [_p, _p, _i64, _p, _i64, _i32, _f64, _f64, _p]),
     "vbcsr_spmm_t": (_int, [_p, _p, _i64, _p, _i64, _i32, _f64, _f64, _p]),

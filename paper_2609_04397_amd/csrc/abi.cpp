@@ -124,6 +124,7 @@ struct DevDir {
   int32_t *blk_prow = nullptr;
   int64_t *colg = nullptr;    // forward direction only
   int64_t n_values = 0, n_values16 = 0;
+  int32_t npanels = 0;        // forward: block rows; transposed: block columns
 };
 
 int env_path() {
@@ -137,8 +138,9 @@ int env_path() {
 }  // namespace
 
 struct vbcsr_mat {
-  int32_t n = 0;
-  int64_t N = 0, nnzb = 0, nnz = 0;
+  int32_t n = 0;       // atoms: block columns (and block rows when square)
+  int32_t n_rows = 0;  // block rows: n, or the owned atoms of a rank-local operator
+  int64_t N = 0, N_rows = 0, nnzb = 0, nnz = 0;
   int32_t n_shapes = 0;
   vbcsr_prec prec = VBCSR_FP64;
   vbcsr_plan_opts opts{};
@@ -218,16 +220,28 @@ size_t span_bytes(int64_t rows, int64_t ld, int32_t nrhs, size_t elem) {
   return ((size_t)(rows - 1) * (size_t)ld + (size_t)nrhs) * elem;
 }
 
-int check_vectors(const vbcsr_mat *A, const void *X, int64_t ldx, const void *Y, int64_t ldy,
-                  int32_t nrhs, bool y_written) {
+// X has xrows rows and Y yrows (N or N_rows, by direction); a vector with no
+// rows may be NULL.
+int check_vectors(const vbcsr_mat *A, const void *X, int64_t xrows, int64_t ldx, const void *Y,
+                  int64_t yrows, int64_t ldy, int32_t nrhs, bool y_written) {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (nrhs <= 0) return fail(VBCSR_EINVAL, "nrhs must be >= 1");
   if (ldx < nrhs || ldy < nrhs) return fail(VBCSR_EINVAL, "leading dimension smaller than nrhs");
-  if (A->N == 0) return VBCSR_OK;
-  if (!X || !Y) return fail(VBCSR_EINVAL, "vector pointer is NULL");
+  if ((xrows > 0 && !X) || (yrows > 0 && !Y)) return fail(VBCSR_EINVAL, "vector pointer is NULL");
   const size_t e = vec_elem(A);
-  if (y_written && ranges_overlap(X, span_bytes(A->N, ldx, nrhs, e), Y, span_bytes(A->N, ldy, nrhs, e)))
+  if (y_written && ranges_overlap(X, span_bytes(xrows, ldx, nrhs, e), Y, span_bytes(yrows, ldy, nrhs, e)))
     return fail(VBCSR_EINVAL, "input and output vectors overlap");
+  return VBCSR_OK;
+}
+
+// Rows of the input and output vectors of direction d (0 forward, 1 adjoint).
+int64_t in_rows(const vbcsr_mat *A, int d) { return d == 0 ? A->N : A->N_rows; }
+int64_t out_rows(const vbcsr_mat *A, int d) { return d == 0 ? A->N_rows : A->N; }
+
+int require_square(const vbcsr_mat *A, const char *where) {
+  if (A && A->n_rows != A->n)
+    return fail(VBCSR_EUNSUPPORTED,
+                std::string(where) + ": needs a square operator (this one is rank-local)");
   return VBCSR_OK;
 }
 
@@ -259,12 +273,12 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
   if (A->prec == VBCSR_FP64) {
     FwdParams<double> p{};
     p.rows = D.rows;
-    p.nrows = A->n;
+    p.nrows = D.npanels;
     p.colx = D.colx;
     p.vals = static_cast<const double *>(D.vals);
     p.X = static_cast<const double *>(X);
     p.ldx = ldx;
-    p.xrows = A->N;
+    p.xrows = in_rows(A, d);
     p.Yin = static_cast<const double *>(Yin);
     p.ldyin = ldyin;
     p.Yout = static_cast<double *>(Yout);
@@ -279,7 +293,7 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
   } else {
     FwdParams<float> p{};
     p.rows = D.rows;
-    p.nrows = A->n;
+    p.nrows = D.npanels;
     p.colx = D.colx;
     p.vals = static_cast<const float *>(D.vals);
     p.hi = D.hi;
@@ -287,7 +301,7 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
     p.vbase16 = D.vbase16;
     p.X = static_cast<const float *>(X);
     p.ldx = ldx;
-    p.xrows = A->N;
+    p.xrows = in_rows(A, d);
     p.Yin = static_cast<const float *>(Yin);
     p.ldyin = ldyin;
     p.Yout = static_cast<float *>(Yout);
@@ -306,14 +320,14 @@ int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Y
 
 int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                  int64_t n_values, const vbcsr_plan_opts *opts, HostPlan &plan,
-                 bool with_columns) {
+                 bool with_columns, int32_t n_rows = -1) {
   std::string err;
   if (opts && (opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
     return fail(VBCSR_EINVAL, "row_order must be one of VBCSR_ORDER_*");
   int rc = validate_graph(n, b, row_ptr, col_idx, n_values, err);
   if (rc) return fail(rc, err);
   build_plan(n, b, row_ptr, col_idx, opts ? opts->row_order : VBCSR_ORDER_AUTO, plan,
-             with_columns);
+             with_columns, n_rows);
   return VBCSR_OK;
 }
 
@@ -322,7 +336,7 @@ int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int3
 int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
                 const int64_t *row_ptr, const int32_t *col_idx, const void *values,
                 bool values_on_device, int64_t n_values, vbcsr_prec prec,
-                const vbcsr_plan_opts *opts, void *stream) {
+                const vbcsr_plan_opts *opts, void *stream, int32_t n_rows = -1) {
   if (!out) return fail(VBCSR_EINVAL, "out is NULL");
   *out = nullptr;
   if (prec != VBCSR_FP64 && prec != VBCSR_FP32 && prec != VBCSR_BF16X3)
@@ -331,7 +345,8 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     return fail(VBCSR_EINVAL, "invalid plan options");
   HostPlan plan;
   // column tables are built on the device from the per-block maps
-  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan, false);
+  int rc = plan_checked(n_atoms, block_sizes, row_ptr, col_idx, n_values, opts, plan, false,
+                        n_rows);
   if (rc) return rc;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -347,7 +362,9 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     }
   } guard{A};
   A->n = n_atoms;
+  A->n_rows = plan.n_rows;
   A->N = plan.N;
+  A->N_rows = plan.N_rows;
   A->nnzb = plan.nnzb;
   A->nnz = plan.nnz;
   A->n_shapes = (int32_t)plan.shapes.size();
@@ -369,6 +386,7 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     DevDir &D = A->dir[d];
     D.n_values = P.n_values;
     D.n_values16 = P.n_values16;
+    D.npanels = (int32_t)P.rows.size();
     if ((rc = upload_into(A, &D.rows, P.rows, s))) return bail(rc);
     if ((rc = alloc_into(A, &D.colx, (size_t)P.n_cols))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
@@ -509,6 +527,38 @@ int vbcsr_create(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   return api_exception("vbcsr_create");
 }
 
+int vbcsr_create_local(vbcsr_mat **out, int32_t n_owned, int32_t n_ghost,
+                       const int32_t *block_sizes, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *values, int64_t n_values, vbcsr_prec prec,
+                       const vbcsr_plan_opts *opts, void *stream) try {
+  if (out) *out = nullptr;
+  if (n_owned < 0 || n_ghost < 0) return fail(VBCSR_EINVAL, "n_owned and n_ghost must be >= 0");
+  if ((int64_t)n_owned + n_ghost > INT32_MAX) return fail(VBCSR_EUNSUPPORTED, "more than 2^31-1 atoms");
+  if (!row_ptr) return fail(VBCSR_EINVAL, "row_ptr is NULL");
+  const int32_t n = n_owned + n_ghost;
+  // the ghost atoms' rows are empty: the same graph as a square one over
+  // owned + ghost atoms, with panels only for the owned rows
+  std::vector<int64_t> rp((size_t)n + 1);
+  std::copy(row_ptr, row_ptr + (size_t)n_owned + 1, rp.begin());
+  std::fill(rp.begin() + n_owned + 1, rp.end(), row_ptr[n_owned]);
+  return create_impl(out, n, block_sizes, rp.data(), col_idx, values, false, n_values, prec, opts,
+                     stream, n_owned);
+} catch (...) {
+  return api_exception("vbcsr_create_local");
+}
+
+int vbcsr_shape(const vbcsr_mat *A, int32_t *n_row_atoms, int32_t *n_col_atoms, int64_t *n_rows,
+                int64_t *n_cols) try {
+  if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (n_row_atoms) *n_row_atoms = A->n_rows;
+  if (n_col_atoms) *n_col_atoms = A->n;
+  if (n_rows) *n_rows = A->N_rows;
+  if (n_cols) *n_cols = A->N;
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_shape");
+}
+
 int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype, void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (dtype != 0 && dtype != 1) return fail(VBCSR_EINVAL, "dtype must be 0 (double) or 1 (float)");
@@ -535,8 +585,9 @@ int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype,
 
 int vbcsr_spmm(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nrhs,
                double alpha, double beta, void *stream) try {
-  int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
-  if (rc || A->N == 0) return rc;
+  int rc = A ? check_vectors(A, X, in_rows(A, 0), ldx, Y, out_rows(A, 0), ldy, nrhs, true)
+             : fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (rc || out_rows(A, 0) == 0) return rc;
   return product(A, 0, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
                  static_cast<hipStream_t>(stream));
 } catch (...) {
@@ -545,8 +596,9 @@ int vbcsr_spmm(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t 
 
 int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_t ldy,
                  int32_t nrhs, double alpha, double beta, void *stream) try {
-  int rc = check_vectors(A, X, ldx, Y, ldy, nrhs, true);
-  if (rc || A->N == 0) return rc;
+  int rc = A ? check_vectors(A, X, in_rows(A, 1), ldx, Y, out_rows(A, 1), ldy, nrhs, true)
+             : fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (rc || out_rows(A, 1) == 0) return rc;
   return product(A, 1, X, ldx, Y, ldy, Y, ldy, nrhs, alpha, beta, nullptr, 0, nullptr,
                  static_cast<hipStream_t>(stream));
 } catch (...) {
@@ -555,24 +607,26 @@ int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_
 
 int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X, int64_t ldx,
                 int32_t nrhs, void *dA, void *stream) try {
-  int rc = check_vectors(A, dY, lddy, X, ldx, nrhs, false);
+  // dY is shaped like the forward output, X like the forward input
+  int rc = A ? check_vectors(A, dY, A->N_rows, lddy, X, A->N, ldx, nrhs, false)
+             : fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (rc) return rc;
   if (A->nnz == 0) return VBCSR_OK;
   if (!dA) return fail(VBCSR_EINVAL, "dA is NULL");
   const size_t e = vec_elem(A);
   const size_t abytes = e * (size_t)A->nnz;
-  if (ranges_overlap(dA, abytes, dY, span_bytes(A->N, lddy, nrhs, e)) ||
+  if (ranges_overlap(dA, abytes, dY, span_bytes(A->N_rows, lddy, nrhs, e)) ||
       ranges_overlap(dA, abytes, X, span_bytes(A->N, ldx, nrhs, e)))
     return fail(VBCSR_EINVAL, "dA overlaps an input");
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t err;
   const DevDir &D = A->dir[0];
   if (A->prec == VBCSR_FP64) {
-    SddmmParams<double> p{D.rows, A->n, D.colx, D.colg, static_cast<const double *>(dY), lddy,
+    SddmmParams<double> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const double *>(dY), lddy,
                           static_cast<const double *>(X), ldx, nrhs, static_cast<double *>(dA)};
     err = launch_sddmm_f64(p, s);
   } else {
-    SddmmParams<float> p{D.rows, A->n, D.colx, D.colg, static_cast<const float *>(dY), lddy,
+    SddmmParams<float> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const float *>(dY), lddy,
                          static_cast<const float *>(X), ldx, nrhs, static_cast<float *>(dA)};
     err = launch_sddmm_f32(p, s);
   }
@@ -584,6 +638,7 @@ int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
 
 int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes) try {
   if (!A || !bytes) return fail(VBCSR_EINVAL, "NULL argument");
+  if (int rc = require_square(A, "vbcsr_cheb_workspace_bytes")) return rc;
   if (nrhs <= 0) return fail(VBCSR_EINVAL, "nrhs must be >= 1");
   if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
   const int64_t vec = ((int64_t)vec_elem(A) * A->N * nrhs + 255) / 256 * 256;
@@ -599,6 +654,7 @@ int vbcsr_cheb_moments(const vbcsr_mat *A, const void *R, int64_t ldr, int32_t n
                        int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
                        void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (int rc = require_square(A, "Chebyshev moments")) return rc;
   if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
   if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
@@ -671,6 +727,7 @@ int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, i
                                int32_t degree, double *mu_host, void *workspace, int64_t ws_bytes,
                                void *stream) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
+  if (int rc = require_square(A, "Chebyshev moments")) return rc;
   if (nrhs <= 0 || nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be in [1, 4096]");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
   if (degree < 0) return fail(VBCSR_EINVAL, "degree must be >= 0");
@@ -760,7 +817,9 @@ int vbcsr_cheb_moments_doubled(const vbcsr_mat *A, const void *R, int64_t ldr, i
 int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev, int64_t ldp,
                     const void *R, int64_t ldr, int32_t nrhs, double *mu_dev, void *workspace,
                     int64_t ws_bytes, void *stream) try {
-  int rc = check_vectors(A, Tk, ldt, Tprev, ldp, nrhs, true);
+  if (int rc = require_square(A, "vbcsr_cheb_step")) return rc;
+  int rc = A ? check_vectors(A, Tk, A->N, ldt, Tprev, A->N, ldp, nrhs, true)
+             : fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (rc) return rc;
   if (nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be <= 4096");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
@@ -801,7 +860,9 @@ int vbcsr_cheb_step(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev
 int vbcsr_cheb_step_noalloc(const vbcsr_mat *A, const void *Tk, int64_t ldt, void *Tprev,
                             int64_t ldp, const void *R, int64_t ldr, int32_t nrhs, double *mu_dev,
                             void *stream) try {
-  int rc = check_vectors(A, Tk, ldt, Tprev, ldp, nrhs, true);
+  if (int rc = require_square(A, "vbcsr_cheb_step_noalloc")) return rc;
+  int rc = A ? check_vectors(A, Tk, A->N, ldt, Tprev, A->N, ldp, nrhs, true)
+             : fail(VBCSR_EINVAL, "matrix handle is NULL");
   if (rc) return rc;
   if (nrhs > 4096) return fail(VBCSR_EINVAL, "nrhs must be <= 4096");
   if (ldr < nrhs) return fail(VBCSR_EINVAL, "ldr smaller than nrhs");
@@ -845,7 +906,7 @@ int vbcsr_cheb_step_noalloc(const vbcsr_mat *A, const void *Tk, int64_t ldt, voi
 int vbcsr_info(const vbcsr_mat *A, int64_t *n_rows, int64_t *nnzb, int64_t *n_values,
                int32_t *n_shapes) try {
   if (!A) return fail(VBCSR_EINVAL, "matrix handle is NULL");
-  if (n_rows) *n_rows = A->N;
+  if (n_rows) *n_rows = A->N_rows;
   if (nnzb) *nnzb = A->nnzb;
   if (n_values) *n_values = A->nnz;
   if (n_shapes) *n_shapes = A->n_shapes;
@@ -868,7 +929,7 @@ int vbcsr_get_structure(const vbcsr_mat *A, int32_t *block_sizes, int64_t *row_p
   if (A->n) {
     HIP_TRY(hipMemcpy(block_sizes, A->b, sizeof(int32_t) * A->n, hipMemcpyDeviceToHost),
             "hipMemcpy");
-    HIP_TRY(hipMemcpy(row_ptr, A->row_ptr, sizeof(int64_t) * (A->n + 1), hipMemcpyDeviceToHost),
+    HIP_TRY(hipMemcpy(row_ptr, A->row_ptr, sizeof(int64_t) * (A->n_rows + 1), hipMemcpyDeviceToHost),
             "hipMemcpy");
   } else if (row_ptr) {
     row_ptr[0] = 0;
@@ -908,6 +969,8 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (!(eps >= 0.0)) return fail(VBCSR_EINVAL, "eps must be >= 0");
   if (A->prec != VBCSR_FP64 || B->prec != VBCSR_FP64)
     return fail(VBCSR_EUNSUPPORTED, "the block product takes FP64 handles");
+  if (int rc2 = require_square(A, "vbcsr_spgemm")) return rc2;
+  if (int rc2 = require_square(B, "vbcsr_spgemm")) return rc2;
   if (A->n != B->n) return fail(VBCSR_EINVAL, "A and B must be over the same atoms");
   if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA ||
                opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))

@@ -118,8 +118,10 @@ struct DirPlan {
 };
 
 struct HostPlan {
-  int32_t n = 0;
-  int64_t N = 0, nnzb = 0, nnz = 0;
+  int32_t n = 0;        // atoms (block columns; block rows of a square operator)
+  int32_t n_rows = 0;   // block rows that may hold blocks: n, or the owned atoms
+                        // of a rank-local operator (the first n_rows atoms)
+  int64_t N = 0, N_rows = 0, nnzb = 0, nnz = 0;
   std::vector<int64_t> off;                   // n+1 scalar row offsets
   RawVec<int64_t> gbase;                      // nnzb+1 graph value offsets
   RawVec<int32_t> blk_row;                    // per graph block: block row i
@@ -135,9 +137,12 @@ int validate_graph(int32_t n, const int32_t *b, const int64_t *row_ptr, const in
 // Build both directions of the plan (assumes validate_graph passed).  With
 // with_columns unset the column tables (colx, colg) are left empty and only
 // their sizes (n_cols) are set; the device builds them from the per-block
-// maps (blk_prow, blk_k0).
+// maps (blk_prow, blk_k0).  n_rows >= 0 (rank-local operators): only atoms
+// below n_rows hold blocks in their rows; the forward direction then has
+// n_rows panels and the transposed one n (default: n_rows = n).
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                int32_t row_order, HostPlan &plan, bool with_columns = true);
+                int32_t row_order, HostPlan &plan, bool with_columns = true,
+                int32_t n_rows = -1);
 
 
 // Symbolic stage of the thresholded block product C = A B over one atom set

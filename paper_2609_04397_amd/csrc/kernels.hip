@@ -1675,6 +1675,49 @@ hipError_t launch_columns(const ColumnParams &p, hipStream_t s) {
 
 
 // ---------------------------------------------------------------------------
+// halo exchange buffers of a rank-local operator
+// ---------------------------------------------------------------------------
+// buf[t, c] = X[rows[t], c]: one thread per element, consecutive threads
+// along c (coalesced row pieces).  Rows outside [0, xrows) are skipped.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rows_pack(const T *__restrict__ X, int64_t xrows,
+                                                        int64_t ldx, const int32_t *__restrict__ rows,
+                                                        int64_t nrows, int32_t nrhs,
+                                                        T *__restrict__ buf, int64_t ldb) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= nrows * nrhs) return;
+  const int64_t t = e / nrhs, c = e - t * nrhs;
+  const int64_t r = rows[t];
+  if (r < 0 || r >= xrows) return;
+  buf[t * ldb + c] = X[r * ldx + c];
+}
+
+// Y[red_rows[u], c] += sum over e in [red_ptr[u], red_ptr[u+1]) of
+// buf[red_pos[e], c], in e order: one thread per (u, c), so every output
+// element has one writer.  Indices outside Y or the buffer are skipped.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_rows_reduce(T *__restrict__ Y, int64_t yrows,
+                                                          int64_t ldy,
+                                                          const int32_t *__restrict__ red_rows,
+                                                          const int64_t *__restrict__ red_ptr,
+                                                          const int64_t *__restrict__ red_pos,
+                                                          int64_t n_red, int64_t brows,
+                                                          const T *__restrict__ buf, int64_t ldb,
+                                                          int32_t nrhs) {
+  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (e >= n_red * nrhs) return;
+  const int64_t u = e / nrhs, c = e - u * nrhs;
+  const int64_t r = red_rows[u];
+  if (r < 0 || r >= yrows) return;
+  T acc = Y[r * ldy + c];
+  for (int64_t q = red_ptr[u]; q < red_ptr[u + 1]; ++q) {
+    const int64_t s = red_pos[q];
+    if (s >= 0 && s < brows) acc += buf[s * ldb + c];
+  }
+  Y[r * ldy + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
 // scratch of the allocation-free entry points
 // ---------------------------------------------------------------------------
 // One copy per GPU, resident from the module's load to the end of the
@@ -1702,6 +1745,42 @@ hipError_t noalloc_scratch(void **ptr, size_t *bytes) {
   *ptr = addr[dev];
   *bytes = kNoAllocScratchBytes;
   return hipSuccess;
+}
+
+
+hipError_t launch_rows_pack(const void *X, int64_t xrows, int64_t ldx, const int32_t *rows,
+                            int64_t nrows, int32_t nrhs, int elem_bytes, void *buf, int64_t ldb,
+                            hipStream_t s) {
+  const int64_t n = nrows * nrhs;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_rows_pack<double>, grid, dim3(kThreads), 0, s,
+                       static_cast<const double *>(X), xrows, ldx, rows, nrows, nrhs,
+                       static_cast<double *>(buf), ldb);
+  else
+    hipLaunchKernelGGL(k_rows_pack<float>, grid, dim3(kThreads), 0, s,
+                       static_cast<const float *>(X), xrows, ldx, rows, nrows, nrhs,
+                       static_cast<float *>(buf), ldb);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_reduce(void *Y, int64_t yrows, int64_t ldy, const int32_t *red_rows,
+                              const int64_t *red_ptr, const int64_t *red_pos, int64_t n_red,
+                              int64_t brows, const void *buf, int64_t ldb, int32_t nrhs,
+                              int elem_bytes, hipStream_t s) {
+  const int64_t n = n_red * nrhs;
+  if (n == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kThreads - 1) / kThreads));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_rows_reduce<double>, grid, dim3(kThreads), 0, s, static_cast<double *>(Y),
+                       yrows, ldy, red_rows, red_ptr, red_pos, n_red, brows,
+                       static_cast<const double *>(buf), ldb, nrhs);
+  else
+    hipLaunchKernelGGL(k_rows_reduce<float>, grid, dim3(kThreads), 0, s, static_cast<float *>(Y),
+                       yrows, ldy, red_rows, red_ptr, red_pos, n_red, brows,
+                       static_cast<const float *>(buf), ldb, nrhs);
+  return hipGetLastError();
 }
 
 }  // namespace vbcsr

@@ -157,6 +157,18 @@ struct ColumnParams {
 };
 hipError_t launch_columns(const ColumnParams &p, hipStream_t s);
 
+// Halo buffers of a rank-local operator: buf[t] = X[rows[t]] (rows outside
+// [0, xrows) skipped), and Y[red_rows[u]] += sum of buf[red_pos[e]] over
+// e in [red_ptr[u], red_ptr[u+1]) in order (indices outside Y or the brows
+// buffer rows skipped).  elem_bytes 8 (double) or 4 (float).
+hipError_t launch_rows_pack(const void *X, int64_t xrows, int64_t ldx, const int32_t *rows,
+                            int64_t nrows, int32_t nrhs, int elem_bytes, void *buf, int64_t ldb,
+                            hipStream_t s);
+hipError_t launch_rows_reduce(void *Y, int64_t yrows, int64_t ldy, const int32_t *red_rows,
+                              const int64_t *red_ptr, const int64_t *red_pos, int64_t n_red,
+                              int64_t brows, const void *buf, int64_t ldb, int32_t nrhs,
+                              int elem_bytes, hipStream_t s);
+
 // Scratch of the allocation-free entry points: a file-scope device array of
 // kNoAllocScratchBytes per GPU.  *ptr receives its address on the current
 // device (looked up with hipGetSymbolAddress on the first call per device).

@@ -157,8 +157,10 @@ static void sort_members(int32_t n, const int32_t *b, Members &M) {
 static void layout_direction(int32_t n, const int32_t *b, const std::vector<int64_t> &off,
                              const Members &M, int64_t nnzb, const RawVec<int64_t> *gbase,
                              const std::vector<int32_t> &order, bool with_columns, DirPlan &d) {
-  d.rows.resize(n);
-  d.vbase16.resize(n);
+  // panels: the atoms of `order` (all n, or the rows that may hold blocks)
+  const int32_t np = (int32_t)order.size();
+  d.rows.resize(np);
+  d.vbase16.resize(np);
   // every graph block belongs to exactly one panel: the fill below writes
   // each entry once
   d.blk_pos.resize(nnzb);
@@ -176,7 +178,7 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
     }
   });
   int64_t vbase = 0, cbase = 0, vbase16 = 0;
-  for (int32_t pi = 0; pi < n; ++pi) {
+  for (int32_t pi = 0; pi < np; ++pi) {
     const int32_t r = order[pi];
     const int32_t h = b[r], K = width[r];
     RowDesc rd{};
@@ -198,7 +200,7 @@ static void layout_direction(int32_t n, const int32_t *b, const std::vector<int6
     d.colx.assign(cbase, 0);
     if (gbase) d.colg.assign(cbase, 0);
   }
-  parallel_rows(n, [&](int32_t p0, int32_t p1) {
+  parallel_rows(np, [&](int32_t p0, int32_t p1) {
     for (int32_t pi = p0; pi < p1; ++pi) {
       const int32_t r = order[pi];
       const RowDesc &rd = d.rows[pi];
@@ -364,11 +366,14 @@ static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const i
 }
 
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
-                int32_t row_order, HostPlan &plan, bool with_columns) {
+                int32_t row_order, HostPlan &plan, bool with_columns, int32_t n_rows) {
+  if (n_rows < 0) n_rows = n;
   plan.n = n;
+  plan.n_rows = n_rows;
   plan.off.assign((size_t)n + 1, 0);
   for (int32_t i = 0; i < n; ++i) plan.off[i + 1] = plan.off[i] + b[i];
   plan.N = plan.off[n];
+  plan.N_rows = plan.off[n_rows];
   plan.nnzb = row_ptr[n];
   const int64_t nnzb = plan.nnzb;
   // graph value offsets: per-row sums, a prefix over rows, then the rows
@@ -455,7 +460,16 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
     }
   });
   sort_members(n, b, M);
-  layout_direction(n, b, plan.off, M, nnzb, &plan.gbase, order, with_columns, plan.fwd);
+  // a rank-local operator has panels only for its first n_rows atoms (the
+  // rest have no blocks in their rows); they keep their processing order
+  std::vector<int32_t> row_order_fwd;
+  if (n_rows < n) {
+    row_order_fwd.reserve((size_t)n_rows);
+    for (int32_t r : order)
+      if (r < n_rows) row_order_fwd.push_back(r);
+  }
+  layout_direction(n, b, plan.off, M, nnzb, &plan.gbase, n_rows < n ? row_order_fwd : order,
+                   with_columns, plan.fwd);
 
   // transposed: panel j holds the blocks (i, j) of block column j, ordered
   // by (b_i, i)

@@ -41,7 +41,11 @@ class Matrix:
     _stamps = 0  # bumped by every value upload; lets autograd detect repacks
 
     def __init__(self, block_sizes, row_ptr, col_idx, values=None, prec: str = "fp64",
-                 path: str = "auto", nrhs_tile: int = 0, row_order: str = "auto"):
+                 path: str = "auto", nrhs_tile: int = 0, row_order: str = "auto",
+                 n_ghost: int = 0):
+        """``n_ghost > 0`` builds a rank-local operator (section 3.1): the
+        first ``len(row_ptr) - 1`` atoms are owned (block rows), the last
+        ``n_ghost`` are ghosts (columns only); see ``vbcsr_create_local``."""
         lib = _lib.load()
         if prec not in _lib.PREC:
             raise ValueError("prec must be one of %s" % list(_lib.PREC))
@@ -53,10 +57,17 @@ class Matrix:
         ci = _np(col_idx, np.int32)
         self.block_sizes, self.row_ptr, self.col_idx = b, rp, ci
         self.n = int(b.shape[0])
-        nnz = int((b[np.repeat(np.arange(self.n), np.diff(rp))].astype(np.int64)
+        n_rows = int(rp.shape[0]) - 1
+        if n_ghost < 0 or (n_ghost == 0 and n_rows != self.n) or \
+                (n_ghost > 0 and n_rows + n_ghost != self.n):
+            raise ValueError("row_ptr needs n_atoms + 1 entries (square) or "
+                             "n_atoms - n_ghost + 1 (rank-local)")
+        nnz = int((b[np.repeat(np.arange(n_rows), np.diff(rp))].astype(np.int64)
                    * b[ci].astype(np.int64)).sum()) if ci.size else 0
         self.n_values = nnz
         self.N = int(b.astype(np.int64).sum())
+        self.n_rows = n_rows
+        self.N_rows = int(b[:n_rows].astype(np.int64).sum())
         opts = _lib.PlanOpts(0, int(nrhs_tile), _lib.PATH[path], _lib.ORDER[row_order])
         host_vals = None
         dev_vals = None
@@ -66,10 +77,16 @@ class Matrix:
             host_vals = _np(values.cpu().numpy() if isinstance(values, torch.Tensor) else values,
                             np.float64)
         h = ctypes.c_void_p()
-        check(lib.vbcsr_create(ctypes.byref(h), self.n, b.ctypes.data, rp.ctypes.data,
-                               ci.ctypes.data if ci.size else None,
-                               host_vals.ctypes.data if host_vals is not None else None,
-                               nnz, _lib.PREC[prec], ctypes.byref(opts), _stream()))
+        if n_ghost > 0:
+            check(lib.vbcsr_create_local(ctypes.byref(h), n_rows, int(n_ghost), b.ctypes.data,
+                                         rp.ctypes.data, ci.ctypes.data if ci.size else None,
+                                         host_vals.ctypes.data if host_vals is not None else None,
+                                         nnz, _lib.PREC[prec], ctypes.byref(opts), _stream()))
+        else:
+            check(lib.vbcsr_create(ctypes.byref(h), self.n, b.ctypes.data, rp.ctypes.data,
+                                   ci.ctypes.data if ci.size else None,
+                                   host_vals.ctypes.data if host_vals is not None else None,
+                                   nnz, _lib.PREC[prec], ctypes.byref(opts), _stream()))
         self._h = h
         Matrix._stamps += 1
         self._stamp = Matrix._stamps
@@ -85,6 +102,7 @@ class Matrix:
         self.device = torch.device("cuda", torch.cuda.current_device())
         inf = self.info()
         self.n, self.N, self.n_values = int(n_atoms), inf["N"], inf["n_values"]
+        self.n_rows, self.N_rows = self.n, self.N
         b = np.empty(self.n, np.int32)
         rp = np.empty(self.n + 1, np.int64)
         ci = np.empty(max(inf["nnzb"], 1), np.int32)
@@ -114,15 +132,16 @@ class Matrix:
             pass
 
     # -- helpers ------------------------------------------------------------
-    def _vec(self, X, name):
+    def _vec(self, X, name, rows=None):
+        rows = self.N if rows is None else rows
         if not isinstance(X, torch.Tensor) or not X.is_cuda:
             raise TypeError("%s must be a CUDA tensor" % name)
         if X.dtype != self.dtype:
             raise TypeError("%s must be %s for a %s matrix" % (name, self.dtype, self.prec))
         if X.dim() == 1:
             X = X.unsqueeze(1)
-        if X.dim() != 2 or X.shape[0] != self.N:
-            raise ValueError("%s must have %d rows" % (name, self.N))
+        if X.dim() != 2 or X.shape[0] != rows:
+            raise ValueError("%s must have %d rows" % (name, rows))
         if X.stride(1) != 1:
             X = X.contiguous()
         return X
@@ -179,19 +198,22 @@ class Matrix:
 
     # -- products -------------------------------------------------------------
     def spmm(self, X, Y=None, alpha=1.0, beta=0.0, transpose=False):
-        """``Y <- alpha * op(A) X + beta * Y`` with op = identity or transpose."""
-        X = self._vec(X, "X")
+        """``Y <- alpha * op(A) X + beta * Y`` with op = identity or transpose
+        (a rank-local operator maps N columns to N_rows rows)."""
+        xr, yr = (self.N_rows, self.N) if transpose else (self.N, self.N_rows)
+        X = self._vec(X, "X", xr)
         nrhs = X.shape[1]
         if Y is None:
-            Y = torch.empty((self.N, nrhs), dtype=self.dtype, device=X.device)
+            Y = torch.empty((yr, nrhs), dtype=self.dtype, device=X.device)
             beta = 0.0
         else:
             if not (isinstance(Y, torch.Tensor) and Y.is_cuda and Y.dtype == self.dtype
-                    and Y.dim() == 2 and Y.shape == (self.N, nrhs) and Y.stride(1) == 1):
-                raise ValueError("Y must be a row-major (N, nrhs) CUDA tensor of the matrix dtype")
+                    and Y.dim() == 2 and Y.shape == (yr, nrhs) and Y.stride(1) == 1):
+                raise ValueError("Y must be a row-major (%d, nrhs) CUDA tensor of the matrix dtype"
+                                 % yr)
         fn = _lib.load().vbcsr_spmm_t if transpose else _lib.load().vbcsr_spmm
-        check(fn(self._h, _ptr(X), X.stride(0) if self.N else nrhs, _ptr(Y),
-                 Y.stride(0) if self.N else nrhs, nrhs, float(alpha), float(beta), _stream()))
+        check(fn(self._h, _ptr(X), X.stride(0) if xr else nrhs, _ptr(Y),
+                 Y.stride(0) if yr else nrhs, nrhs, float(alpha), float(beta), _stream()))
         return Y
 
     def spmm_t(self, X, Y=None, alpha=1.0, beta=0.0):
@@ -206,13 +228,13 @@ class Matrix:
 
     def sddmm(self, dY, X, out=None):
         """``dA_ij = dY_i X_j^T`` on the stored blocks (graph order)."""
-        dY = self._vec(dY, "dY")
+        dY = self._vec(dY, "dY", self.N_rows)
         X = self._vec(X, "X")
         if dY.shape[1] != X.shape[1]:
             raise ValueError("dY and X need the same number of columns")
         if out is None:
             out = torch.empty(self.n_values, dtype=self.dtype, device=X.device)
-        check(_lib.load().vbcsr_sddmm(self._h, _ptr(dY), dY.stride(0) if self.N else dY.shape[1],
+        check(_lib.load().vbcsr_sddmm(self._h, _ptr(dY), dY.stride(0) if self.N_rows else dY.shape[1],
                                       _ptr(X), X.stride(0) if self.N else X.shape[1], X.shape[1],
                                       _ptr(out), _stream()))
         return out
