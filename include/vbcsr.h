@@ -62,7 +62,7 @@ enum {
 };
 
 enum { VBCSR_PATH_AUTO = 0, VBCSR_PATH_VEC = 1, VBCSR_PATH_MFMA = 2 };
-enum { VBCSR_ORDER_AUTO = 0, VBCSR_ORDER_ATOM = 1, VBCSR_ORDER_RCM = 2 };
+enum { VBCSR_ORDER_AUTO = 0, VBCSR_ORDER_ATOM = 1, VBCSR_ORDER_RCM = 2, VBCSR_ORDER_CLUSTER = 3 };
 
 /* Planner options; zero fields mean "choose automatically".
  *   path:        VBCSR_PATH_* -- force the vector-FMA or the matrix-core
@@ -72,14 +72,15 @@ enum { VBCSR_ORDER_AUTO = 0, VBCSR_ORDER_ATOM = 1, VBCSR_ORDER_RCM = 2 };
  *   rows_per_wg: reserved, must be 0.
  *   row_order:   VBCSR_ORDER_* -- order in which the device lays out and
  *                processes the block rows (and block columns, for the
- *                adjoint): atom order, or reverse Cuthill-McKee of the
- *                symmetrised block graph, so that consecutive panels share
- *                input rows in cache.  Results are the same up to rounding
- *                (each output still has one writer summing its row in panel
- *                order); moments of the Chebyshev helpers are reduced in the
- *                processing order.  AUTO takes RCM when it at least halves
- *                the mean processing distance between the two atoms of a
- *                block, else atom order.                                      */
+ *                adjoint): atom order; reverse Cuthill-McKee of the
+ *                symmetrised block graph; or clusters of 256 atoms grown
+ *                breadth-first over that graph, each seeded next to the
+ *                previous one, so that the panels processed together gather
+ *                the input rows of one compact cluster and its halo while
+ *                they are in cache.  AUTO is the clustered order.  Results
+ *                are the same up to rounding (each output still has one
+ *                writer summing its row in panel order); moments of the
+ *                Chebyshev helpers are reduced in the processing order.       */
 typedef struct {
   int32_t rows_per_wg;
   int32_t nrhs_tile;

@@ -24,7 +24,7 @@ CODE_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EDUP", -4: "ENOMEM", -5:
 
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 PATH = {"auto": 0, "vec": 1, "mfma": 2}
-ORDER = {"auto": 0, "atom": 1, "rcm": 2}
+ORDER = {"auto": 0, "atom": 1, "rcm": 2, "cluster": 3}
 DAMPING = {"none": 0, "jackson": 1}
 PHASE = {"R": 0, "R+tau": 1}
 

@@ -322,7 +322,7 @@ int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int3
                  int64_t n_values, const vbcsr_plan_opts *opts, HostPlan &plan,
                  bool with_columns, int32_t n_rows = -1) {
   std::string err;
-  if (opts && (opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
+  if (opts && (opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_CLUSTER))
     return fail(VBCSR_EINVAL, "row_order must be one of VBCSR_ORDER_*");
   int rc = validate_graph(n, b, row_ptr, col_idx, n_values, err);
   if (rc) return fail(rc, err);
@@ -623,11 +623,13 @@ int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
   const DevDir &D = A->dir[0];
   if (A->prec == VBCSR_FP64) {
     SddmmParams<double> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const double *>(dY), lddy,
-                          static_cast<const double *>(X), ldx, nrhs, static_cast<double *>(dA)};
+                          static_cast<const double *>(X), ldx, nrhs, static_cast<double *>(dA),
+                          A->N};
     err = launch_sddmm_f64(p, s);
   } else {
     SddmmParams<float> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const float *>(dY), lddy,
-                         static_cast<const float *>(X), ldx, nrhs, static_cast<float *>(dA)};
+                         static_cast<const float *>(X), ldx, nrhs, static_cast<float *>(dA),
+                         A->N};
     err = launch_sddmm_f32(p, s);
   }
   if (err != hipSuccess) return hip_fail(err, "sddmm kernel launch");
@@ -973,7 +975,7 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (int rc2 = require_square(B, "vbcsr_spgemm")) return rc2;
   if (A->n != B->n) return fail(VBCSR_EINVAL, "A and B must be over the same atoms");
   if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA ||
-               opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_RCM))
+               opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_CLUSTER))
     return fail(VBCSR_EINVAL, "invalid plan options");
   vbcsr_spgemm_stats st{};
   hipStream_t s = static_cast<hipStream_t>(stream);

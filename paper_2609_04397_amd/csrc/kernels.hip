@@ -1159,6 +1159,124 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
 }
 
 // ---------------------------------------------------------------------------
+// block-sampled dY X^T with the X rows of each tile staged in LDS
+// ---------------------------------------------------------------------------
+// Same products, accumulation order and output map as k_sddmm_mfma; only the
+// way X reaches the B operand differs.  A tile's 16 X rows (CW right-hand
+// sides each) are loaded with whole-row pieces -- 64 / (CW / EPL) rows per
+// load instruction, EPL elements (16 bytes) per lane -- instead of 16 rows
+// per instruction, written to a wave-private LDS tile (rows padded by EPL
+// elements, so the fragment reads of the 16 rows hit distinct banks) and read
+// back in the MFMA fragment order.  X is addressed through one buffer
+// descriptor (all of X within 2^31 bytes): reads past its end return zero.
+template <typename T, int CW>
+__global__ void __launch_bounds__(kThreads) k_sddmm_lds(SddmmParams<T> P) {
+  using V = typename Frag<T>::type;
+  constexpr int NCH = CW / 32;                 // 32-wide chunks per pass
+  constexpr int EPL = 16 / (int)sizeof(T);     // elements per 16-byte piece
+  constexpr int LPR = CW / EPL;                // lanes per staged row
+  constexpr int RPI = 64 / LPR;                // rows per staging load
+  constexpr int RS = CW + EPL;                 // LDS row stride (elements)
+  static_assert(CW == 32 || CW == 64, "pass width");
+  __shared__ __align__(16) T xs_all[kWaves * 16 * RS];
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
+  if (row >= P.nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15;
+  const int kq = lane >> 4;
+  T *xs = xs_all + wave_id() * 16 * RS;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  if (K == 0) return;
+  const int ntiles = (K + 15) >> 4;
+  const int npass = (P.nrhs + CW - 1) / CW;
+  const int32_t *__restrict__ cx = P.colx + rd.cbase;
+  const int64_t *__restrict__ cg = P.colg + rd.cbase;
+  const __amdgpu_buffer_rsrc_t rx =
+      panel_rsrc(P.X, (uint32_t)(P.xrows * P.ldx * (int64_t)sizeof(T)));
+  // contraction order inside a 32-wide chunk (the same for both operands):
+  // FP64 c = 8 l + 2 kq + e (l < 4, e < 2), FP32 c = 8 kq + s
+  constexpr bool PAIR = sizeof(T) == 8;
+  const int kofs = PAIR ? 2 * kq : 8 * kq;
+  auto rhs = [&](int ch, int s) { return ch * 32 + kofs + (PAIR ? 8 * (s >> 1) + (s & 1) : s); };
+  const int sr = lane / LPR;            // staging: row within a load
+  const int se = (lane % LPR) * EPL;    // staging: first element of the piece
+  for (int mt = 0; mt * 16 < b; ++mt) {
+    const int p = mt * 16 + m;
+    const T *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
+    T af[NCH][8];
+    auto load_af = [&](int c0) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int c = c0 + rhs(ch, s);
+          const T v = dyrow[min(c, P.nrhs - 1)];
+          af[ch][s] = (p < b && c < P.nrhs) ? v : T(0);
+        }
+    };
+    if (npass == 1) load_af(0);
+    for (int j = 0; j < ntiles; ++j) {
+      // lane r (and r + 16, r + 32, r + 48) holds tile column r
+      const int kc = j * 16 + m;
+      const int kk = kc < K ? kc : K - 1;
+      const int32_t xr = cx[kk];
+      const int64_t g = cg[kk];
+      V acc0 = V{}, acc1 = V{};
+      for (int pass = 0; pass < npass; ++pass) {
+        const int c0 = pass * CW;
+        if (npass > 1) load_af(c0);
+        // stage the tile's 16 rows x CW right-hand sides
+        typename Vec16<T>::type v[16 / RPI];
+#pragma unroll
+        for (int it = 0; it < 16 / RPI; ++it) {
+          const int r = it * RPI + sr;
+          const int32_t xrow = __shfl(xr, r, 64);
+          const int c = c0 + se;
+          const uint32_t off = (j * 16 + r < K && c < P.nrhs)
+                                   ? (uint32_t)(((int64_t)xrow * P.ldx + c) * (int64_t)sizeof(T))
+                                   : 0x80000000u;
+          v[it] = __builtin_bit_cast(typename Vec16<T>::type,
+                                     __builtin_amdgcn_raw_buffer_load_b128(rx, off, 0, 0));
+        }
+#pragma unroll
+        for (int it = 0; it < 16 / RPI; ++it) {
+          const int r = it * RPI + sr;
+          const int c = c0 + se;
+          T *e = reinterpret_cast<T *>(&v[it]);
+#pragma unroll
+          for (int q = 0; q < EPL; ++q) e[q] = c + q < P.nrhs ? e[q] : T(0);
+          *reinterpret_cast<typename Vec16<T>::type *>(xs + r * RS + se) = v[it];
+        }
+        wave_lds_sync();
+        T bv[NCH][8];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) bv[ch][s] = xs[m * RS + rhs(ch, s)];
+        wave_lds_sync();  // every read done before the next staging
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+          for (int s = 0; s < 8; s += 2) {
+            acc0 = mfma(af[ch][s], bv[ch][s], acc0);
+            acc1 = mfma(af[ch][s + 1], bv[ch][s + 1], acc1);
+          }
+      }
+      if (kc < K) {
+        const int64_t base = g >> 7;
+        const int bj = (int)(g & 127);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pr = mt * 16 + dst_row<T>(kq, i);
+          if (pr < b) P.dA[base + (int64_t)pr * bj] = acc0[i] + acc1[i];
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column dot products in FP64 and their fixed-order reduction
 // ---------------------------------------------------------------------------
 constexpr int kDotRows = 256;
@@ -1555,6 +1673,14 @@ template <typename T>
 hipError_t launch_sddmm_t(const SddmmParams<T> &p, hipStream_t s) {
   if (p.nrows == 0) return hipSuccess;
   const dim3 grid((unsigned)product_workgroups(p.nrows));
+  // X rows staged through LDS when all of X fits one buffer descriptor
+  if (p.xrows * p.ldx * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    if (p.nrhs <= 32)
+      hipLaunchKernelGGL((k_sddmm_lds<T, 32>), grid, dim3(kThreads), 0, s, p);
+    else
+      hipLaunchKernelGGL((k_sddmm_lds<T, 64>), grid, dim3(kThreads), 0, s, p);
+    return hipGetLastError();
+  }
   // right-hand sides beyond the register-resident chunks are loaded per tile
   if (p.nrhs <= 32)
     hipLaunchKernelGGL((k_sddmm_mfma<T, 1>), grid, dim3(kThreads), 0, s, p);

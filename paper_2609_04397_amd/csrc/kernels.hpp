@@ -77,6 +77,7 @@ struct SddmmParams {
   int64_t ldx;
   int32_t nrhs;
   T *dA;
+  int64_t xrows;         // rows of X (columns of the operator)
 };
 hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s);
 hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s);

@@ -365,6 +365,69 @@ static std::vector<int32_t> rcm_order(int32_t n, const int64_t *row_ptr, const i
   return order;
 }
 
+// Clustered order: the atoms are taken in compact clusters of up to S atoms,
+// each grown breadth-first over not yet taken atoms of the symmetrised block
+// graph (and listed in ascending atom order), the next cluster seeded on the
+// frontier of the previous one.  Panels
+// processed together then gather the input rows of one cluster and its halo,
+// which stay in the XCD's L2 while the cluster is processed, and consecutive
+// clusters share halos.  Deterministic (sequential, neighbours in stored
+// order).
+// Atoms per cluster of the clustered order (measured: 64 to 4,096 within a
+// few per cent of each other on the lattice, the zincblende particle and the
+// random three-species structure; 256 best or tied on most products).
+constexpr int32_t kClusterAtoms = 256;
+
+static std::vector<int32_t> cluster_order(int32_t n, const int64_t *row_ptr,
+                                          const int32_t *col_idx, const Transpose &T,
+                                          int32_t S) {
+  std::vector<char> seen((size_t)n, 0);
+  std::vector<int32_t> order;
+  order.reserve((size_t)n);
+  std::vector<int32_t> queue;
+  int32_t scan = 0, next_seed = -1;
+  while ((int32_t)order.size() < n) {
+    int32_t seed = next_seed;
+    if (seed < 0 || seen[seed]) {
+      while (scan < n && seen[scan]) ++scan;
+      seed = scan;
+    }
+    next_seed = -1;
+    const size_t c0 = order.size();
+    queue.clear();
+    queue.push_back(seed);
+    seen[seed] = 1;
+    size_t head = 0;
+    while (head < queue.size()) {
+      const int32_t v = queue[head++];
+      order.push_back(v);
+      if ((int64_t)(order.size() - c0) >= S) break;
+      for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k) {
+        const int32_t u = col_idx[k];
+        if (!seen[u]) {
+          seen[u] = 1;
+          queue.push_back(u);
+        }
+      }
+      for (int64_t e = T.ptr[v]; e < T.ptr[v + 1]; ++e) {
+        const int32_t u = T.row[e];
+        if (!seen[u]) {
+          seen[u] = 1;
+          queue.push_back(u);
+        }
+      }
+    }
+    // atoms queued but not taken go back to the pool; the first of them
+    // (adjacent to this cluster) seeds the next one
+    for (size_t q = head; q < queue.size(); ++q) seen[queue[q]] = 0;
+    if (head < queue.size()) next_seed = queue[head];
+    // inside a cluster, ascending atoms: consecutive output rows (and
+    // values in the caller's order) where the input order already has them
+    std::sort(order.begin() + c0, order.end());
+  }
+  return order;
+}
+
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                 int32_t row_order, HostPlan &plan, bool with_columns, int32_t n_rows) {
   if (n_rows < 0) n_rows = n;
@@ -419,33 +482,10 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   transpose_graph(n, row_ptr, col_idx, T);
   std::vector<int32_t> order((size_t)n);
   std::iota(order.begin(), order.end(), 0);
-  if (row_order != VBCSR_ORDER_ATOM) {
-    std::vector<int32_t> rcm = rcm_order(n, row_ptr, col_idx, T);
-    // AUTO keeps the caller's order unless RCM at least halves the mean
-    // distance, in processing order, between the two atoms of a block
-    // (a lattice or a spatially sorted input already has locality); the
-    // distances are summed exactly, in integers
-    bool take = row_order == VBCSR_ORDER_RCM;
-    if (!take && nnzb > 0) {
-      std::vector<int32_t> pos((size_t)n);
-      for (int32_t t = 0; t < n; ++t) pos[rcm[t]] = t;
-      unsigned __int128 d_atom = 0, d_rcm = 0;
-      std::mutex mu;
-      parallel_rows(n, [&](int32_t r0, int32_t r1) {
-        unsigned __int128 da = 0, dr = 0;
-        for (int32_t i = r0; i < r1; ++i)
-          for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
-            const int32_t j = col_idx[k];
-            da += (uint64_t)(i > j ? i - j : j - i);
-            dr += (uint64_t)(pos[i] > pos[j] ? pos[i] - pos[j] : pos[j] - pos[i]);
-          }
-        std::lock_guard<std::mutex> lock(mu);
-        d_atom += da;
-        d_rcm += dr;
-      });
-      take = 2 * d_rcm <= d_atom;
-    }
-    if (take) order.swap(rcm);
+  if (row_order == VBCSR_ORDER_CLUSTER || row_order == VBCSR_ORDER_AUTO) {
+    order = cluster_order(n, row_ptr, col_idx, T, kClusterAtoms);
+  } else if (row_order == VBCSR_ORDER_RCM) {
+    order = rcm_order(n, row_ptr, col_idx, T);
   }
 
   // forward: panel i holds the blocks of block row i, ordered by (b_j, j)

@@ -87,7 +87,7 @@ int vbcsr_zmat_create(vbcsr_zmat **out, int32_t n_atoms, const int32_t *block_si
   if (prec == VBCSR_BF16X3) return zfail(VBCSR_EUNSUPPORTED, "complex operators are FP64 or FP32");
   if (prec != VBCSR_FP64 && prec != VBCSR_FP32) return zfail(VBCSR_EINVAL, "unknown precision");
   if (opts && (opts->rows_per_wg != 0 || opts->row_order < VBCSR_ORDER_AUTO ||
-               opts->row_order > VBCSR_ORDER_RCM))
+               opts->row_order > VBCSR_ORDER_CLUSTER))
     return zfail(VBCSR_EINVAL, "invalid plan options");
   if (n_images < 1 || !shifts) return zfail(VBCSR_EINVAL, "need n_images >= 1 and shifts");
   // the image graph: blocks (i, j, m); the same (i, j) may repeat under other images

@@ -176,31 +176,65 @@ def _processing_positions(op, fwd):
     return pos
 
 
-def test_row_order_rcm_and_auto(lib):
+def test_row_order_rcm_cluster_and_auto(lib):
     """RCM is a permutation that shortens the processing distance of coupled
-    atoms of a randomly ordered structure; AUTO takes it there and keeps the
-    lattice order of a lattice."""
+    atoms of a randomly ordered structure; the clustered order is a
+    permutation whose clusters of 256 consecutive atoms are connected; AUTO
+    is the clustered order; every order keeps each row's blocks contiguous."""
     from workloads.core import random_cube
     op = random_cube(3000, 0.05, [(1, 600), (4, 1200), (9, 1200)], r_cut=5.0, decay=2.0, seed=7)
-    dist = {}
-    for order in ("atom", "rcm", "auto"):
+    dist, pos_of = {}, {}
+    for order in ("atom", "rcm", "cluster", "auto"):
         fwd = np.zeros(op.nnzb, np.int64)
         tr = np.zeros(op.nnzb, np.int64)
         rc, _, _, pv = _plan(lib, op.b, op.row_ptr, op.col_idx, op.nnz, fwd, tr, order=order)
         assert rc == 0
         pos = _processing_positions(op, fwd)
         assert np.array_equal(np.sort(pos), np.arange(op.n))
+        pos_of[order] = pos
         dist[order] = np.abs(pos[op.block_rows] - pos[op.col_idx]).mean()
         # blocks of one row stay contiguous and ordered by (b_j, j) in any order
         key = np.lexsort((op.col_idx, op.b[op.col_idx], pos[op.block_rows]))
         assert np.all(np.diff(fwd[key]) > 0)
     assert dist["rcm"] <= 0.5 * dist["atom"]
-    assert dist["auto"] == dist["rcm"]
-    lat = sc_lattice(6, 5, seed=1)
-    fwd = np.zeros(lat.nnzb, np.int64)
-    rc, *_ = _plan(lib, lat.b, lat.row_ptr, lat.col_idx, lat.nnz, fwd, order="auto")
-    assert rc == 0
-    assert np.array_equal(_processing_positions(lat, fwd), np.arange(lat.n))
+    assert np.array_equal(pos_of["auto"], pos_of["cluster"])
+    assert np.array_equal(_cluster_reference(op.n, op.row_ptr, op.col_idx, 256),
+                          np.argsort(pos_of["cluster"]))
+
+
+def _cluster_reference(n, rp, ci, S):
+    """The clustered order from its definition: clusters of up to S atoms
+    (listed ascending), each grown breadth-first over untaken atoms (neighbours: the row's
+    columns in stored order, then the column's rows ascending), seeded at the
+    first queued but untaken atom of the previous cluster, else at the
+    lowest untaken atom."""
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    col_rows = [[] for _ in range(n)]
+    for i, j in zip(rows, ci):
+        col_rows[j].append(i)
+    taken = np.zeros(n, bool)
+    order, seed = [], None
+    while len(order) < n:
+        if seed is None or taken[seed]:
+            seed = int(np.argmin(taken))
+        cluster, queue, queued = [], [seed], {seed}
+        head = 0
+        while head < len(queue) and len(cluster) < S:
+            v = queue[head]
+            head += 1
+            cluster.append(v)
+            if len(cluster) == S:
+                break
+            for u in list(ci[rp[v]:rp[v + 1]]) + col_rows[v]:
+                if not taken[u] and u not in queued and u not in cluster:
+                    queued.add(u)
+                    queue.append(u)
+        for v in cluster:
+            taken[v] = True
+        order += sorted(cluster)
+        rest = [u for u in queue[head:] if not taken[u]]
+        seed = rest[0] if rest else None
+    return np.array(order)
 
 
 def test_row_order_rejects_unknown(lib):

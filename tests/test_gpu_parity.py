@@ -180,15 +180,17 @@ def test_nonfinite_values_stay_in_their_rows(prec, path, nrhs):
     A.close()
 
 
+@pytest.mark.parametrize("order", ["rcm", "cluster"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
-def test_row_order_does_not_change_results(prec):
-    """Processing the panels in RCM order instead of atom order leaves every
-    product bit for bit the same (one wave still sums each output row in the
-    same panel order) and matches the oracle; moments agree to rounding."""
-    op = random_pattern(5, 60, bset=(1, 4, 9, 13), density=0.12, empty_rows=3, unsorted=True)
+def test_row_order_does_not_change_results(prec, order):
+    """Processing the panels in RCM or clustered order instead of atom order
+    leaves every product bit for bit the same (one wave still sums each
+    output row in the same panel order) and matches the oracle; moments agree
+    to rounding."""
+    op = random_pattern(5, 600, bset=(1, 4, 9, 13), density=0.012, empty_rows=3, unsorted=True)
     rng = np.random.default_rng(12)
     A1 = Matrix.from_operator(op, prec=prec, row_order="atom")
-    A2 = Matrix.from_operator(op, prec=prec, row_order="rcm")
+    A2 = Matrix.from_operator(op, prec=prec, row_order=order)
     for nrhs in (1, 2, 8, 32, 64):
         print("case order", prec, nrhs, flush=True)
         X = dev(rng.standard_normal((op.N, nrhs)), prec)
@@ -205,7 +207,7 @@ def test_row_order_does_not_change_results(prec):
     ops = scaled(op, inf_norm_scale(op))
     R = rng.standard_normal((op.N, 5))
     B1 = Matrix.from_operator(ops, prec=prec, row_order="atom")
-    B2 = Matrix.from_operator(ops, prec=prec, row_order="rcm")
+    B2 = Matrix.from_operator(ops, prec=prec, row_order=order)
     m1 = B1.cheb_moments(dev(R, prec), 16)
     m2 = B2.cheb_moments(dev(R, prec), 16)
     assert np.max(np.abs(m1 - m2)) <= 1e-13 * np.max(np.abs(m1[0]))
