@@ -187,26 +187,24 @@ void free_all(vbcsr_mat *A) {
 
 // Pack graph-order values (device) into both directions' pages.
 int pack_all(vbcsr_mat *A, const void *src, int src_dtype, hipStream_t s) {
+  PackParams pp{};
+  pp.b = A->b;
+  pp.blk_row = A->blk_row;
+  pp.col_idx = A->col_idx;
+  pp.gbase = A->gbase;
+  pp.nnzb = A->nnzb;
+  pp.dst_kind = A->prec == VBCSR_BF16X3 ? 2 : A->prec == VBCSR_FP64 ? 0 : 1;
   for (int d = 0; d < 2; ++d) {
-    DevDir &D = A->dir[d];
-    PackParams pp{};
-    pp.b = A->b;
-    pp.blk_row = A->blk_row;
-    pp.col_idx = A->col_idx;
-    pp.gbase = A->gbase;
-    pp.pos = D.blk_pos;
-    pp.k0 = D.blk_k0;
-    pp.prow = D.blk_prow;
-    pp.vbase16 = D.vbase16;
-    pp.nnzb = A->nnzb;
-    pp.transposed = d;
-    hipError_t e;
-    if (A->prec == VBCSR_BF16X3)
-      e = launch_pack(pp, src, src_dtype, D.hi, 2, D.lo, s);
-    else
-      e = launch_pack(pp, src, src_dtype, D.vals, A->prec == VBCSR_FP64 ? 0 : 1, nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
+    const DevDir &D = A->dir[d];
+    pp.dir[d].pos = D.blk_pos;
+    pp.dir[d].k0 = D.blk_k0;
+    pp.dir[d].prow = D.blk_prow;
+    pp.dir[d].vbase16 = D.vbase16;
+    pp.dir[d].dst = A->prec == VBCSR_BF16X3 ? static_cast<void *>(D.hi) : D.vals;
+    pp.dir[d].dst_lo = D.lo;
   }
+  hipError_t e = launch_pack(pp, src, src_dtype, s);
+  if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
   return VBCSR_OK;
 }
 

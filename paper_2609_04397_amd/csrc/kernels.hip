@@ -1012,37 +1012,108 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
 // ---------------------------------------------------------------------------
 // value packing: graph order (row-major blocks) -> pages
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src, int src_dtype,
-                                                   void *dst, int dst_kind, uint16_t *dst_lo) {
-  const int64_t k = (int64_t)blockIdx.x * kWaves + wave_id();
-  if (k >= P.nnzb) return;
+// One wave per run of kPackRun consecutive graph blocks (their values are
+// contiguous in graph order): lane l takes elements l, l + 64, ... of the run,
+// finds its block among the run's value offsets and writes the value to one
+// direction's pages per sweep -- column-major blocks in the forward panels,
+// row-major blocks in the transposed ones.
+constexpr int kPackRun = 8;
+
+__device__ __forceinline__ void pack_store(const PackDir &D, int kind, int64_t pos, int k0,
+                                           int64_t vb16, int h, int r, int c, double v) {
+  if (kind == 2) {
+    const int col = k0 + c;
+    const int64_t a = vb16 + (int64_t)(col >> 3) * 8 * h + r * 8 + (col & 7);
+    const float f = (float)v;
+    const unsigned short hb = bf16_rne(f);
+    static_cast<uint16_t *>(D.dst)[a] = hb;
+    D.dst_lo[a] = bf16_rne(f - bf16_to_f32(hb));
+  } else {
+    const int64_t a = pos + (int64_t)c * h + r;
+    if (kind == 0)
+      static_cast<double *>(D.dst)[a] = v;
+    else
+      static_cast<float *>(D.dst)[a] = (float)v;
+  }
+}
+
+template <int SRC, int KIND>  // SRC 0/1: double/float source; KIND: dst_kind
+__global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src) {
+  const int64_t k0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
+  if (k0 >= P.nnzb) return;
   const int lane = threadIdx.x & 63;
-  const int i = P.blk_row[k], j = P.col_idx[k];
-  const int bi = P.b[i], bj = P.b[j];
-  const int h = P.transposed ? bj : bi;
-  const int64_t sb = P.gbase[k];
-  const int64_t pos = P.pos[k];
-  const int k0 = P.k0[k];
-  const int64_t vb16 = dst_kind == 2 ? P.vbase16[P.prow[k]] : 0;
-  for (int e = lane; e < bi * bj; e += 64) {
-    const int p = e / bj, q = e - p * bj;  // source element (p, q)
-    const double val = src_dtype == 0 ? static_cast<const double *>(src)[sb + e]
-                                      : (double)static_cast<const float *>(src)[sb + e];
-    const int r = P.transposed ? q : p;    // panel row
-    const int c = P.transposed ? p : q;    // panel column relative to k0
-    if (dst_kind == 2) {
-      const int col = k0 + c;
-      const int64_t a = vb16 + (int64_t)(col >> 3) * 8 * h + r * 8 + (col & 7);
-      const float f = (float)val;
-      const unsigned short hb = bf16_rne(f);
-      static_cast<uint16_t *>(dst)[a] = hb;
-      dst_lo[a] = bf16_rne(f - bf16_to_f32(hb));
-    } else {
-      const int64_t a = pos + (int64_t)c * h + r;
-      if (dst_kind == 0)
-        static_cast<double *>(dst)[a] = val;
-      else
-        static_cast<float *>(dst)[a] = (float)val;
+  const int nb = (int)min((int64_t)kPackRun, P.nnzb - k0);
+  // lanes 0 .. nb-1 read one block's map each
+  int bi = 0, bj = 0, kf = 0, kt = 0;
+  int64_t g = 0, pf = 0, pt = 0, vf = 0, vt = 0;
+  if (lane < nb) {
+    const int64_t k = k0 + lane;
+    bi = P.b[P.blk_row[k]];
+    bj = P.b[P.col_idx[k]];
+    g = P.gbase[k];
+    pf = P.dir[0].pos[k];
+    pt = P.dir[1].pos[k];
+    if (KIND == 2) {
+      kf = P.dir[0].k0[k];
+      kt = P.dir[1].k0[k];
+      vf = P.dir[0].vbase16[P.dir[0].prow[k]];
+      vt = P.dir[1].vbase16[P.dir[1].prow[k]];
+    }
+  }
+  const int64_t g0 = __shfl(g, 0, 64);
+  int rs[kPackRun];  // run-relative first value of each block (blocks past nb unused)
+  int rbi[kPackRun], rbj[kPackRun], rkf[kPackRun], rkt[kPackRun];
+  int64_t rpf[kPackRun], rpt[kPackRun], rvf[kPackRun], rvt[kPackRun];
+#pragma unroll
+  for (int t = 0; t < kPackRun; ++t) {
+    rs[t] = (int)(__shfl(g, t, 64) - g0);
+    rbi[t] = __shfl(bi, t, 64);
+    rbj[t] = __shfl(bj, t, 64);
+    rpf[t] = __shfl(pf, t, 64);
+    rpt[t] = __shfl(pt, t, 64);
+    rkf[t] = __shfl(kf, t, 64);
+    rkt[t] = __shfl(kt, t, 64);
+    rvf[t] = __shfl(vf, t, 64);
+    rvt[t] = __shfl(vt, t, 64);
+  }
+  const int len = (int)(__shfl(g + (int64_t)bi * bj, nb - 1, 64) - g0);
+  // Two sweeps over the run, each in the element order in which one
+  // direction's writes are contiguous: row-major (the order of the source)
+  // for the transposed FP64/FP32 pages and the forward BF16 pages, then
+  // column-major for the others, whose (strided) source reads then hit the
+  // lines the first sweep brought into cache.
+  constexpr bool bf = KIND == 2;
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    const int d = (sweep == 0) == bf ? 0 : 1;  // direction written in this sweep
+    for (int e = lane; e < len; e += 64) {
+      // block of value e: the last block starting at or before it
+      int t = 0;
+#pragma unroll
+      for (int u = 1; u < kPackRun; ++u) t = (u < nb && rs[u] <= e) ? u : t;
+      int b1 = rbi[0], b2 = rbj[0], c1 = rkf[0], c2 = rkt[0], st = rs[0];
+      int64_t q1 = rpf[0], q2 = rpt[0], w1 = rvf[0], w2 = rvt[0];
+#pragma unroll
+      for (int u = 1; u < kPackRun; ++u)
+        if (u == t) {
+          b1 = rbi[u]; b2 = rbj[u]; c1 = rkf[u]; c2 = rkt[u]; st = rs[u];
+          q1 = rpf[u]; q2 = rpt[u]; w1 = rvf[u]; w2 = rvt[u];
+        }
+      const int loc = e - st;
+      int p, q;  // source element (p, q) of the b1 x b2 row-major block
+      if (sweep == 0) {
+        p = loc / b2;
+        q = loc - p * b2;
+      } else {
+        q = loc / b1;
+        p = loc - q * b1;
+      }
+      const int64_t at = g0 + st + (int64_t)p * b2 + q;
+      const double v = SRC == 0 ? static_cast<const double *>(src)[at]
+                                : (double)static_cast<const float *>(src)[at];
+      if (d == 0)  // forward panel of atom i: height b_i, row p, column k0 + q
+        pack_store(P.dir[0], KIND, q1, c1, w1, b1, p, q, v);
+      else         // transposed panel of atom j: height b_j, row q, column k0 + p
+        pack_store(P.dir[1], KIND, q2, c2, w2, b2, q, p, v);
     }
   }
 }
@@ -1661,11 +1732,19 @@ hipError_t launch_spmm_f32(const FwdParams<float> &p, Kind kind, int tile, hipSt
   return launch_spmm_t<float>(p, kind, tile, s);
 }
 
-hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void *dst,
-                       int dst_kind, uint16_t *dst_lo, hipStream_t s) {
+hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipStream_t s) {
   if (p.nnzb == 0) return hipSuccess;
-  const dim3 grid((unsigned)((p.nnzb + kWaves - 1) / kWaves));
-  hipLaunchKernelGGL(k_pack, grid, dim3(kThreads), 0, s, p, src, src_dtype, dst, dst_kind, dst_lo);
+  const int64_t waves = (p.nnzb + kPackRun - 1) / kPackRun;
+  const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves));
+  const int sel = src_dtype * 3 + p.dst_kind;
+  switch (sel) {
+    case 0: hipLaunchKernelGGL((k_pack<0, 0>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 1: hipLaunchKernelGGL((k_pack<0, 1>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 2: hipLaunchKernelGGL((k_pack<0, 2>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 3: hipLaunchKernelGGL((k_pack<1, 0>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 4: hipLaunchKernelGGL((k_pack<1, 1>), grid, dim3(kThreads), 0, s, p, src); break;
+    default: hipLaunchKernelGGL((k_pack<1, 2>), grid, dim3(kThreads), 0, s, p, src); break;
+  }
   return hipGetLastError();
 }
 

@@ -47,22 +47,25 @@ int64_t product_workgroups(int64_t nrows);
 hipError_t launch_spmm_f64(const FwdParams<double> &p, Kind kind, int tile, hipStream_t s);
 hipError_t launch_spmm_f32(const FwdParams<float> &p, Kind kind, int tile, hipStream_t s);
 
-// Graph-order values -> pages of one direction.
+// Graph-order values -> the pages of both directions, in one pass.
+struct PackDir {
+  const int64_t *pos;       // per graph block: page offset of its first value
+  const int32_t *k0;        // per graph block: first panel column
+  const int32_t *prow;      // per graph block: panel (processing order)
+  const int64_t *vbase16;   // per panel: offset in the BF16 pages
+  void *dst;                // double or float pages, or the BF16 hi pages
+  uint16_t *dst_lo;         // BF16 lo pages (BF16X3 only)
+};
 struct PackParams {
   const int32_t *b;         // per atom
   const int32_t *blk_row;   // per graph block
   const int32_t *col_idx;   // per graph block
-  const int64_t *gbase;     // per graph block
-  const int64_t *pos;       // per graph block: page offset of first value
-  const int32_t *k0;        // per graph block: first panel column
-  const int32_t *prow;      // per graph block: panel atom
-  const int64_t *vbase16;   // per atom (BF16 pages)
+  const int64_t *gbase;     // per graph block: first value in graph order
   int64_t nnzb;
-  int transposed;           // 0: forward panels, 1: transposed panels
+  int dst_kind;             // 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages
+  PackDir dir[2];           // 0: forward panels (column-major blocks), 1: transposed
 };
-hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, void *dst,
-                       int dst_kind, uint16_t *dst_lo, hipStream_t s);
-// dst_kind: 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages (dst = hi)
+hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipStream_t s);
 
 // dA (graph order) = block-sampled dY X^T, over the forward panels.
 template <typename T>
