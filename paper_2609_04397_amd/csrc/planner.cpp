@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 #include <mutex>
@@ -428,6 +430,45 @@ static std::vector<int32_t> cluster_order(int32_t n, const int64_t *row_ptr,
   return order;
 }
 
+// Planner statistics on stderr (environment variable VBCSR_LOG set and not
+// "0"): sizes, shape classes, the values the panel layout adds (alignment
+// padding of the FP64/FP32 pages, 8-column padding of the BF16 pages), and
+// how evenly the panels divide the work (largest and mean panel in values,
+// the 4-panel workgroups' largest over mean).
+static void log_plan(const HostPlan &plan, int32_t row_order) {
+  const char *names[] = {"auto (clustered)", "atom", "rcm", "clustered"};
+  const DirPlan &F = plan.fwd;
+  int64_t vmax = 0, vsum = 0, wmax = 0, wsum = 0, nw = 0, wcur = 0;
+  for (size_t r = 0; r < F.rows.size(); ++r) {
+    const int64_t v = (int64_t)F.rows[r].b * F.rows[r].K;
+    vmax = std::max(vmax, v);
+    vsum += v;
+    wcur += v;
+    if (r % 4 == 3 || r + 1 == F.rows.size()) {
+      wmax = std::max(wmax, wcur);
+      wsum += wcur;
+      ++nw;
+      wcur = 0;
+    }
+  }
+  const double np = std::max<double>(1.0, (double)F.rows.size());
+  std::fprintf(stderr,
+               "vbcsr plan: %d atoms (%d block rows), N %lld, %lld blocks, %lld values, order %s\n"
+               "vbcsr plan: %zu shape classes:",
+               plan.n, plan.n_rows, (long long)plan.N, (long long)plan.nnzb, (long long)plan.nnz,
+               names[row_order >= 0 && row_order <= 3 ? row_order : 0], plan.shapes.size());
+  for (const auto &sh : plan.shapes) std::fprintf(stderr, " %dx%d:%d", sh[0], sh[1], sh[2]);
+  std::fprintf(stderr,
+               "\nvbcsr plan: pages %lld values (+%.3f %% alignment), BF16 pages %lld (+%.3f %%)\n"
+               "vbcsr plan: panel values max %lld mean %.1f; workgroup (4 panels) max/mean %.2f; "
+               "transposed panels %zu\n",
+               (long long)F.n_values, 100.0 * (double)(F.n_values - plan.nnz) / std::max<int64_t>(1, plan.nnz),
+               (long long)F.n_values16,
+               100.0 * (double)(F.n_values16 - plan.nnz) / std::max<int64_t>(1, plan.nnz),
+               (long long)vmax, (double)vsum / np,
+               nw ? (double)wmax / ((double)wsum / (double)nw) : 0.0, plan.tr.rows.size());
+}
+
 void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32_t *col_idx,
                 int32_t row_order, HostPlan &plan, bool with_columns, int32_t n_rows) {
   if (n_rows < 0) n_rows = n;
@@ -518,6 +559,7 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
   M.mblk.swap(T.blk);
   sort_members(n, b, M);
   layout_direction(n, b, plan.off, M, nnzb, nullptr, order, with_columns, plan.tr);
+  if (const char *lg = std::getenv("VBCSR_LOG"); lg && *lg && *lg != '0') log_plan(plan, row_order);
 }
 
 }  // namespace vbcsr

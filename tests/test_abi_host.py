@@ -470,3 +470,43 @@ def test_host_allocation_failure_is_a_status(lib):
     rc, rc2, msg = r.stdout.strip().split(" ", 2)
     assert int(rc) == _lib.VBCSR_ENOMEM and "vbcsr_plan_host" in msg, r.stdout
     assert int(rc2) == 0
+
+
+_LOG_CHILD = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+sys.path.insert(0, sys.argv[1] + "/tests")
+from paper_2609_04397_amd import _lib
+from test_abi_host import _plan
+from workloads import make_config
+op, _ = make_config("C5", scale=0.05, nrhs=1)
+rc, ns, shapes, pv = _plan(_lib.load(), op.b, op.row_ptr, op.col_idx, op.nnz, order="cluster")
+print(rc, ns, int(pv))
+"""
+
+
+def test_planner_log_statistics():
+    """VBCSR_LOG prints the planner's statistics on stderr: sizes, the shape
+    classes with their counts, the layout's padding and the balance of the
+    panels; without it the planner prints nothing."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, VBCSR_LOG="1")
+    r = subprocess.run([sys.executable, "-c", _LOG_CHILD, root], capture_output=True, text=True,
+                       env=env, timeout=120)
+    assert r.returncode == 0, r.stderr
+    rc, ns, pv = map(int, r.stdout.split())
+    assert rc == 0 and ns == 9
+    lines = [l for l in r.stderr.splitlines() if l.startswith("vbcsr plan:")]
+    assert len(lines) == 4
+    assert "5000 atoms" in lines[0] and "order clustered" in lines[0]
+    classes = lines[1].split(":", 2)[2].split()
+    assert len(classes) == 9 and sum(int(c.split(":")[1]) for c in classes[1:]) > 0
+    assert "pages %d values" % pv in lines[2]
+    env.pop("VBCSR_LOG")
+    r = subprocess.run([sys.executable, "-c", _LOG_CHILD, root], capture_output=True, text=True,
+                       env=env, timeout=120)
+    assert r.returncode == 0 and "vbcsr plan" not in r.stderr
