@@ -386,7 +386,9 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     D.n_values16 = P.n_values16;
     D.npanels = (int32_t)P.rows.size();
     if ((rc = upload_into(A, &D.rows, P.rows, s))) return bail(rc);
-    if ((rc = alloc_into(A, &D.colx, (size_t)P.n_cols))) return bail(rc);
+    // 4 entries of slack: a kernel may read a panel's indices in groups of
+    // four (never using those past the panel)
+    if ((rc = alloc_into(A, &D.colx, (size_t)P.n_cols + 4))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_k0, P.blk_k0, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_prow, P.blk_prow, s))) return bail(rc);

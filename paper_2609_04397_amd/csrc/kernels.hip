@@ -1348,6 +1348,149 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_lds(SddmmParams<T> P) {
 }
 
 // ---------------------------------------------------------------------------
+// block-sampled dY X^T in FP64 with the X rows loaded straight into LDS
+// ---------------------------------------------------------------------------
+// Same products, accumulation order and output map as k_sddmm_mfma, for
+// nrhs = 32 NCH.  A step is one tile and one 32-wide chunk of right-hand
+// sides.  Its 16 X row pieces (256 bytes each) go from memory to a 4 KiB
+// wave-private LDS buffer by buffer-to-LDS loads, which hold no registers
+// while in flight; the next step's loads are issued as soon as the current
+// B fragments are in registers, so they overlap this step's matrix
+// instructions.  A tile's outputs are stored during the first step of the
+// next tile, from a second accumulator pair, after that step's loads are
+// issued: the wait for the loads of a step never waits on stores issued
+// after them.
+//
+// LDS layout: load instruction it (0..3) writes 64 lanes x 16 bytes to
+// consecutive addresses; lane l (q = l >> 4) fetches row r = 4 q + it, piece
+// (l & 15) ^ r, so row r sits at (r & 3) * 1 KiB + (r >> 2) * 256 bytes with
+// its pieces permuted, and the fragment reads of 16 rows at one piece index
+// hit 16 distinct bank groups.  Lane l reads the X row indices of its four
+// rows with one 16-byte load (rows past the panel are not loaded).  Column indices and output maps are loaded two tiles ahead.
+// Requires X within 2^31 bytes (one buffer descriptor).
+template <int NCH>
+__global__ void __launch_bounds__(kThreads) k_sddmm_dma(SddmmParams<double> P) {
+  using LdsPtr = __attribute__((address_space(3))) void *;
+  constexpr int CW = 32;
+  __shared__ __align__(16) double xs_all[kWaves * 16 * CW];
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
+  if (row >= P.nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15;
+  const int kq = lane >> 4;
+  double *xs = xs_all + wave_id() * 16 * CW;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  if (K == 0) return;
+  const int ntiles = (K + 15) >> 4;
+  const int nsteps = ntiles * NCH;
+  const int64_t *__restrict__ cg = P.colg + rd.cbase;
+  const __amdgpu_buffer_rsrc_t rx =
+      panel_rsrc(P.X, (uint32_t)(P.xrows * P.ldx * (int64_t)sizeof(double)));
+  // the panel's indices rounded up to a group of four (the table has four
+  // entries of slack), so a group is either wholly in range or wholly past it
+  const __amdgpu_buffer_rsrc_t rc =
+      panel_rsrc(P.colx + rd.cbase, (uint32_t)((K + 3) & ~3) * 4u);
+  // X row indices of rows 4 kq .. 4 kq + 3 of tile j
+  auto rows_of = [&](int j) {
+    return __builtin_bit_cast(v4u32, __builtin_amdgcn_raw_buffer_load_b128(
+                                         rc, (uint32_t)(j * 16 + 4 * kq) * 4u, 0, 0));
+  };
+  auto gmap_of = [&](int j) { return cg[min(j * 16 + m, K - 1)]; };
+  const int sslot = lane & 15;
+  auto issue = [&](int s, v4u32 xr) {
+    const int j = s / NCH, ch = s % NCH;
+#pragma unroll
+    for (int it = 0; it < 4; ++it) {
+      const int r = 4 * kq + it;
+      const int pc = sslot ^ r;
+      const uint32_t off =
+          j * 16 + r < K ? (uint32_t)(((int64_t)(int32_t)xr[it] * P.ldx + ch * CW + 2 * pc) *
+                                      (int64_t)sizeof(double))
+                         : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LdsPtr)(xs + it * 4 * CW), 16, off, 0, 0, 0);
+    }
+  };
+  const double *xm = xs + (m & 3) * 4 * CW + (m >> 2) * CW;   // row m in LDS
+  for (int mt = 0; mt * 16 < b; ++mt) {
+    const int p = mt * 16 + m;
+    const double *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
+    // A fragments: lane (m, kq) holds c = 32 ch + 8 l + 2 kq + e (l < 4, e < 2)
+    double af[NCH][8];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const double v = dyrow[ch * CW + 2 * kq + 8 * (s >> 1) + (s & 1)];
+        af[ch][s] = p < b ? v : 0.0;
+      }
+    // index registers: tiles j (cur), j + 1 (nxt), j + 2 (nn, loaded during
+    // tile j); they move along at the start of a tile, after the step's wait,
+    // so no copy waits on a load in flight
+    v4u32 xr_cur = rows_of(0), xr_nxt = rows_of(1), xr_nn = xr_nxt;
+    int64_t g_cur = gmap_of(0), g_nxt = gmap_of(1), g_nn = g_nxt, g_done = 0;
+    issue(0, xr_cur);
+    v4d acc0 = v4d{}, acc1 = v4d{};
+    double done[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < ntiles; ++j) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int s = j * NCH + ch;
+        double bv[8];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          const double2 v = *reinterpret_cast<const double2 *>(xm + 2 * ((kq + 4 * l) ^ m));
+          bv[2 * l] = v.x;
+          bv[2 * l + 1] = v.y;
+        }
+        // the fragments are in registers before the buffer is refilled
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unchanged
+        if (ch == 0 && j > 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) done[i] = acc0[i] + acc1[i];
+          acc0 = v4d{};
+          acc1 = v4d{};
+          g_done = g_cur;
+          xr_cur = xr_nxt;
+          g_cur = g_nxt;
+          xr_nxt = xr_nn;
+          g_nxt = g_nn;
+        }
+        if (s + 1 < nsteps) issue(s + 1, ch == NCH - 1 ? xr_nxt : xr_cur);
+        if (ch == 0) {
+          xr_nn = rows_of(j + 2);
+          g_nn = gmap_of(j + 2);
+          if (j > 0 && (j - 1) * 16 + m < K) {   // outputs of tile j - 1
+            const int64_t base = g_done >> 7;
+            const int bj = (int)(g_done & 127);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int pr = mt * 16 + dst_row<double>(kq, i);
+              if (pr < b) P.dA[base + (int64_t)pr * bj] = done[i];
+            }
+          }
+        }
+#pragma unroll
+        for (int l = 0; l < 8; l += 2) {
+          acc0 = mfma(af[ch][l], bv[l], acc0);
+          acc1 = mfma(af[ch][l + 1], bv[l + 1], acc1);
+        }
+      }
+    }
+    // outputs of the last tile
+    if ((ntiles - 1) * 16 + m < K) {
+      const int64_t base = g_cur >> 7;
+      const int bj = (int)(g_cur & 127);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pr = mt * 16 + dst_row<double>(kq, i);
+        if (pr < b) P.dA[base + (int64_t)pr * bj] = acc0[i] + acc1[i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // column dot products in FP64 and their fixed-order reduction
 // ---------------------------------------------------------------------------
 constexpr int kDotRows = 256;
@@ -1754,6 +1897,14 @@ hipError_t launch_sddmm_t(const SddmmParams<T> &p, hipStream_t s) {
   const dim3 grid((unsigned)product_workgroups(p.nrows));
   // X rows staged through LDS when all of X fits one buffer descriptor
   if (p.xrows * p.ldx * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    if (std::is_same<T, double>::value && (p.nrhs == 32 || p.nrhs == 64)) {
+      const auto &pd = reinterpret_cast<const SddmmParams<double> &>(p);
+      if (p.nrhs == 32)
+        hipLaunchKernelGGL((k_sddmm_dma<1>), grid, dim3(kThreads), 0, s, pd);
+      else
+        hipLaunchKernelGGL((k_sddmm_dma<2>), grid, dim3(kThreads), 0, s, pd);
+      return hipGetLastError();
+    }
     if (p.nrhs <= 32)
       hipLaunchKernelGGL((k_sddmm_lds<T, 32>), grid, dim3(kThreads), 0, s, p);
     else

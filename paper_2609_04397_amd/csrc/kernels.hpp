@@ -72,7 +72,7 @@ template <typename T>
 struct SddmmParams {
   const RowDesc *rows;   // forward panels
   int32_t nrows;
-  const int32_t *colx;   // per panel column: X row
+  const int32_t *colx;   // per panel column: X row (4 entries of slack follow the table)
   const int64_t *colg;   // per panel column: (graph offset of block + q) << 7 | b_j
   const T *dY;
   int64_t lddy;
