@@ -1013,10 +1013,19 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
 // value packing: graph order (row-major blocks) -> pages
 // ---------------------------------------------------------------------------
 // One wave per run of kPackRun consecutive graph blocks (their values are
-// contiguous in graph order): lane l takes elements l, l + 64, ... of the run,
-// finds its block among the run's value offsets and writes the value to one
-// direction's pages per sweep -- column-major blocks in the forward panels,
-// row-major blocks in the transposed ones.
+// contiguous in graph order): lane l takes elements l, l + 64, ... of the
+// run, so every lane is busy whatever the block sizes and the loads of
+// different elements are independent (the loop is unrolled four times to keep
+// four in flight per lane).  A lane finds its block by comparing the element
+// with the run's block starts (wave-uniform, in scalar registers) and reads
+// the block's map from a wave-private LDS table.  For the FP64/FP32 pages one
+// sweep in row-major order (the order of the source) writes the transposed
+// pages as a contiguous copy and the forward pages (each block transposed)
+// inside each block's own contiguous range.  BF16 pages (8-column groups)
+// take one sweep per direction, each in the order in which its writes are
+// contiguous.  Row and column of an element come from a reciprocal of the
+// block width, corrected by one step (exact for offsets below 2^12 and
+// widths up to 64).
 constexpr int kPackRun = 8;
 
 __device__ __forceinline__ void pack_store(const PackDir &D, int kind, int64_t pos, int k0,
@@ -1037,83 +1046,90 @@ __device__ __forceinline__ void pack_store(const PackDir &D, int kind, int64_t p
   }
 }
 
+struct PackRec {       // one block of a run, in LDS
+  int32_t start;       // run-relative first value (graph order)
+  int32_t bi, bj;
+  int32_t kf, kt;      // BF16: first panel column, forward / transposed
+  int32_t pad[3];
+  int64_t pf, pt;      // page offset, forward / transposed
+  int64_t vf, vt;      // BF16: panel base in the BF16 pages, forward / transposed
+};
+static_assert(sizeof(PackRec) == 64, "PackRec layout");
+
 template <int SRC, int KIND>  // SRC 0/1: double/float source; KIND: dst_kind
 __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src) {
+  __shared__ PackRec tab_all[kWaves * kPackRun];
   const int64_t k0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
   if (k0 >= P.nnzb) return;
   const int lane = threadIdx.x & 63;
   const int nb = (int)min((int64_t)kPackRun, P.nnzb - k0);
-  // lanes 0 .. nb-1 read one block's map each
-  int bi = 0, bj = 0, kf = 0, kt = 0;
-  int64_t g = 0, pf = 0, pt = 0, vf = 0, vt = 0;
+  PackRec *tab = tab_all + wave_id() * kPackRun;
+  // lanes 0 .. nb-1 read one block's map each into the table
+  int64_t g = 0;
+  int n = 0;
+  PackRec r{};
   if (lane < nb) {
     const int64_t k = k0 + lane;
-    bi = P.b[P.blk_row[k]];
-    bj = P.b[P.col_idx[k]];
+    r.bi = P.b[P.blk_row[k]];
+    r.bj = P.b[P.col_idx[k]];
     g = P.gbase[k];
-    pf = P.dir[0].pos[k];
-    pt = P.dir[1].pos[k];
+    r.pf = P.dir[0].pos[k];
+    r.pt = P.dir[1].pos[k];
     if (KIND == 2) {
-      kf = P.dir[0].k0[k];
-      kt = P.dir[1].k0[k];
-      vf = P.dir[0].vbase16[P.dir[0].prow[k]];
-      vt = P.dir[1].vbase16[P.dir[1].prow[k]];
+      r.kf = P.dir[0].k0[k];
+      r.kt = P.dir[1].k0[k];
+      r.vf = P.dir[0].vbase16[P.dir[0].prow[k]];
+      r.vt = P.dir[1].vbase16[P.dir[1].prow[k]];
     }
+    n = r.bi * r.bj;
   }
-  const int64_t g0 = __shfl(g, 0, 64);
-  int rs[kPackRun];  // run-relative first value of each block (blocks past nb unused)
-  int rbi[kPackRun], rbj[kPackRun], rkf[kPackRun], rkt[kPackRun];
-  int64_t rpf[kPackRun], rpt[kPackRun], rvf[kPackRun], rvt[kPackRun];
+  const int64_t g0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(g >> 32), 0) << 32) |
+                               (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)g, 0));
+  const int start = (int)(g - g0);   // run-relative first value (lanes < nb)
+  if (lane < nb) {
+    r.start = start;
+    tab[lane] = r;
+  }
+  wave_lds_sync();
+  int st[kPackRun];   // block starts (wave-uniform; past nb: beyond the run)
+  const int len = __builtin_amdgcn_readlane(start + n, nb - 1);
 #pragma unroll
-  for (int t = 0; t < kPackRun; ++t) {
-    rs[t] = (int)(__shfl(g, t, 64) - g0);
-    rbi[t] = __shfl(bi, t, 64);
-    rbj[t] = __shfl(bj, t, 64);
-    rpf[t] = __shfl(pf, t, 64);
-    rpt[t] = __shfl(pt, t, 64);
-    rkf[t] = __shfl(kf, t, 64);
-    rkt[t] = __shfl(kt, t, 64);
-    rvf[t] = __shfl(vf, t, 64);
-    rvt[t] = __shfl(vt, t, 64);
-  }
-  const int len = (int)(__shfl(g + (int64_t)bi * bj, nb - 1, 64) - g0);
-  // Two sweeps over the run, each in the element order in which one
-  // direction's writes are contiguous: row-major (the order of the source)
-  // for the transposed FP64/FP32 pages and the forward BF16 pages, then
-  // column-major for the others, whose (strided) source reads then hit the
-  // lines the first sweep brought into cache.
-  constexpr bool bf = KIND == 2;
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    const int d = (sweep == 0) == bf ? 0 : 1;  // direction written in this sweep
+  for (int u = 0; u < kPackRun; ++u) st[u] = u < nb ? __builtin_amdgcn_readlane(start, u) : len;
+  auto load = [&](int64_t at) {
+    return SRC == 0 ? static_cast<const double *>(src)[at]
+                    : (double)static_cast<const float *>(src)[at];
+  };
+  // sweep 0 in row-major order, sweep 1 (BF16 only) in column-major order
+  for (int sweep = 0; sweep < (KIND == 2 ? 2 : 1); ++sweep) {
+#pragma unroll 4
     for (int e = lane; e < len; e += 64) {
-      // block of value e: the last block starting at or before it
       int t = 0;
 #pragma unroll
-      for (int u = 1; u < kPackRun; ++u) t = (u < nb && rs[u] <= e) ? u : t;
-      int b1 = rbi[0], b2 = rbj[0], c1 = rkf[0], c2 = rkt[0], st = rs[0];
-      int64_t q1 = rpf[0], q2 = rpt[0], w1 = rvf[0], w2 = rvt[0];
-#pragma unroll
-      for (int u = 1; u < kPackRun; ++u)
-        if (u == t) {
-          b1 = rbi[u]; b2 = rbj[u]; c1 = rkf[u]; c2 = rkt[u]; st = rs[u];
-          q1 = rpf[u]; q2 = rpt[u]; w1 = rvf[u]; w2 = rvt[u];
-        }
-      const int loc = e - st;
-      int p, q;  // source element (p, q) of the b1 x b2 row-major block
-      if (sweep == 0) {
-        p = loc / b2;
+      for (int u = 1; u < kPackRun; ++u) t += e >= st[u] ? 1 : 0;
+      const PackRec &rt = tab[t];
+      const int b1 = rt.bi, b2 = rt.bj;
+      const int loc = e - rt.start;
+      int p, q;
+      if (sweep == 0) {   // row-major: p = loc / b2
+        p = (int)((float)loc * __builtin_amdgcn_rcpf((float)b2));
         q = loc - p * b2;
-      } else {
-        q = loc / b1;
+        if (q >= b2) { ++p; q -= b2; }
+      } else {            // column-major: q = loc / b1
+        q = (int)((float)loc * __builtin_amdgcn_rcpf((float)b1));
         p = loc - q * b1;
+        if (p >= b1) { ++q; p -= b1; }
       }
-      const int64_t at = g0 + st + (int64_t)p * b2 + q;
-      const double v = SRC == 0 ? static_cast<const double *>(src)[at]
-                                : (double)static_cast<const float *>(src)[at];
-      if (d == 0)  // forward panel of atom i: height b_i, row p, column k0 + q
-        pack_store(P.dir[0], KIND, q1, c1, w1, b1, p, q, v);
-      else         // transposed panel of atom j: height b_j, row q, column k0 + p
-        pack_store(P.dir[1], KIND, q2, c2, w2, b2, q, p, v);
+      const double v = load(g0 + rt.start + (int64_t)p * b2 + q);
+      if (KIND != 2) {
+        // transposed panel of atom j: height b_j, row q, column k0 + p
+        pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v);
+        // forward panel of atom i: height b_i, row p, column k0 + q
+        pack_store(P.dir[0], KIND, rt.pf, 0, 0, b1, p, q, v);
+      } else if (sweep == 0) {
+        pack_store(P.dir[0], KIND, rt.pf, rt.kf, rt.vf, b1, p, q, v);
+      } else {
+        pack_store(P.dir[1], KIND, rt.pt, rt.kt, rt.vt, b2, q, p, v);
+      }
     }
   }
 }
