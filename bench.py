@@ -96,6 +96,8 @@ def parse():
                     help="only run the block product records (G1, A A) and print them")
     ap.add_argument("--kpm", action="store_true",
                     help="only run the KPM density-of-states records and print them")
+    ap.add_argument("--orders", action="store_true",
+                    help="time the products of C3 and C5 in each processing order and exit")
     ap.add_argument("--kspace", action="store_true",
                     help="only run the reciprocal-space operator records and print them")
     return ap.parse_args()
@@ -406,10 +408,11 @@ def main():
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
-    if args.spgemm or args.kpm or args.kspace:
+    if args.spgemm or args.kpm or args.kspace or args.orders:
         recs = (spgemm_records(with_cpu=not args.no_cpu) if args.spgemm else []) + \
             (kpm_records(with_cpu=not args.no_cpu) if args.kpm else []) + \
-            (kspace_records() if args.kspace else [])
+            (kspace_records() if args.kspace else []) + \
+            (order_records() if args.orders else [])
         for rec in recs:
             print(json.dumps(rec), flush=True)
         return
@@ -679,6 +682,41 @@ def run_sweep(path):
     for rec in kspace_records():
         emit(rec)
     out.close()
+
+
+def order_records():
+    """The planner's processing orders side by side: FP64 products and
+    block-sampled products of the zincblende particle (C3, atoms in lattice
+    generation order) and of the 100,000-atom structure (C5, atoms in random
+    order), with the panels in atom order, reverse Cuthill-McKee order and
+    clustered order (median of 7 after 3)."""
+    import torch
+    from paper_2609_04397_amd import Matrix
+    from workloads import make_config
+
+    dev = torch.device("cuda", 0)
+    recs = []
+    for name, cases in (("C3", ((1, "spmm"), (8, "spmm"), (64, "spmm"), (64, "sddmm"))),
+                        ("C5", ((1, "spmm"), (32, "spmm"), (32, "sddmm")))):
+        op, _ = make_config(name, nrhs=1)
+        for order in ("atom", "rcm", "cluster"):
+            A = Matrix.from_operator(op, row_order=order)
+            for nrhs, kind in cases:
+                X = torch.randn((op.N, nrhs), dtype=torch.float64, device=dev)
+                if kind == "spmm":
+                    Y = torch.empty_like(X)
+                    ms = _time_call(lambda: A.spmm(X, Y))
+                else:
+                    dA = torch.empty(op.nnz, dtype=torch.float64, device=dev)
+                    ms = _time_call(lambda: A.sddmm(X, X, dA))
+                rec = {"workload": name, "op": kind, "prec": "fp64", "order": order, "nrhs": nrhs,
+                       "ms": round(ms, 4)}
+                print("orders", json.dumps(rec), file=sys.stderr, flush=True)
+                recs.append(rec)
+                del X
+            A.close()
+        del op
+    return recs
 
 
 def kspace_records():

@@ -77,10 +77,12 @@ enum { VBCSR_ORDER_AUTO = 0, VBCSR_ORDER_ATOM = 1, VBCSR_ORDER_RCM = 2, VBCSR_OR
  *                breadth-first over that graph, each seeded next to the
  *                previous one, so that the panels processed together gather
  *                the input rows of one compact cluster and its halo while
- *                they are in cache.  AUTO is the clustered order.  Results
- *                are the same up to rounding (each output still has one
- *                writer summing its row in panel order); moments of the
- *                Chebyshev helpers are reduced in the processing order.       */
+ *                they are in cache.  AUTO is the clustered order.  Product
+ *                and SDDMM results do not depend on the order (each output
+ *                has one writer, which sums its row over the panel's columns
+ *                in the same order whatever the processing order); moments
+ *                of the Chebyshev helpers are reduced in the processing
+ *                order, so they agree up to rounding.                         */
 typedef struct {
   int32_t rows_per_wg;
   int32_t nrhs_tile;
