@@ -24,6 +24,9 @@ PATTERNS = {
     "wide": dict(seed=2, n=24, bset=(2, 5, 16, 17, 20, 33), density=0.3, empty_rows=1),
     "big": dict(seed=3, n=10, bset=(64, 31, 48), density=0.5),
     "scalar": dict(seed=4, n=300, bset=(1,), density=0.03, empty_rows=10, unsorted=True),
+    # blocks of exactly 16 columns (the widest that leave the block-sampled
+    # product's output window whole) next to 7-wide ones
+    "sixteen": dict(seed=6, n=36, bset=(7, 16), density=0.3, empty_rows=2, unsorted=True),
 }
 
 
