@@ -357,8 +357,8 @@ typedef struct {
   int64_t nnzb;          /* blocks of C after the final filter                   */
   int64_t products;      /* block products A_ik B_kj evaluated                   */
   double flops;          /* sum over evaluated products of 2 b_i b_k b_j         */
-  double ms_norms;       /* structure copy-back and block norms of A and B      */
-  double ms_symbolic;    /* host symbolic stage and upload of its lists         */
+  double ms_norms;       /* block sizes copy-back and block norms of A and B    */
+  double ms_symbolic;    /* device symbolic stage, C's pattern back to the host */
   double ms_numeric;     /* numeric kernel (device events around it)            */
   double ms_filter;      /* final filter: norms back and compaction             */
   double ms_build;       /* planning and packing of C                           */
@@ -369,10 +369,11 @@ typedef struct {
  * Paper: section 3.2, equation 2 (C_ij = sum_k A_ik B_kj) and equation 3
  * (||C_ij|| <= sum_k ||A_ik|| ||B_kj||).  Stages:
  *   1. block norms of A and B (Frobenius, on the device; only when eps > 0);
- *   2. symbolic stage on the host: the candidates of row i are the columns j
- *      of the rows k of B with a block (i, k) in A; a candidate is rejected
- *      when U_ij = sum_k ||A_ik|| ||B_kj|| (summed over k in A's stored order)
- *      is below eps.  Kept columns are ascending in every row of C;
+ *   2. symbolic stage on the device: the candidates of row i are the columns
+ *      j of the rows k of B with a block (i, k) in A; a candidate is rejected
+ *      when U_ij = sum_k ||A_ik|| ||B_kj|| (summed over k in A's stored order,
+ *      each product and sum rounded separately) is below eps.  Kept columns
+ *      are ascending in every row of C;
  *   3. numeric stage on the device, one wave per output block: the products
  *      A_ik B_kj of the block in A's stored order of k, on matrix cores, FP64;
  *   4. final filter: computed blocks whose Frobenius norm is below eps are
@@ -383,10 +384,10 @@ typedef struct {
  *   eps     block-norm threshold, >= 0
  *   opts    planner options of C (may be NULL)
  *   stats   may be NULL
- * Synchronises `stream` (the symbolic stage needs the norms on the host).
+ * Synchronises `stream` (C's pattern is planned on the host).
  * Errors: EINVAL (null arguments, different atoms, eps < 0 or NaN, bad
- * options), EUNSUPPORTED (non-FP64 handles, or C outside vbcsr_create's
- * limits), ENOMEM, EHIP.
+ * options), EUNSUPPORTED (non-FP64 handles, 2^31 or more candidate block
+ * products, or C outside vbcsr_create's limits), ENOMEM, EHIP.
  */
 int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double eps,
                  const vbcsr_plan_opts *opts, vbcsr_spgemm_stats *stats, void *stream);

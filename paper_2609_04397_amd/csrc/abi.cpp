@@ -983,20 +983,13 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   TempAllocs tmp;
   int rc;
 
-  // structure and page positions back to the host
+  // block sizes back to the host (the handles must share them)
   auto t0 = clk::now();
-  std::vector<int32_t> b, bb, aci, bci;
-  std::vector<int64_t> arp, brp, apos, bpos;
-  if ((rc = d2h(b, A->b, n, s)) || (rc = d2h(bb, B->b, n, s)) ||
-      (rc = d2h(arp, A->row_ptr, (size_t)n + 1, s)) || (rc = d2h(brp, B->row_ptr, (size_t)n + 1, s)) ||
-      (rc = d2h(aci, A->col_idx, A->nnzb, s)) || (rc = d2h(bci, B->col_idx, B->nnzb, s)) ||
-      (rc = d2h(apos, A->dir[1].blk_pos, A->nnzb, s)) ||
-      (rc = d2h(bpos, B->dir[0].blk_pos, B->nnzb, s)))
-    return rc;
+  std::vector<int32_t> b, bb;
+  if ((rc = d2h(b, A->b, n, s)) || (rc = d2h(bb, B->b, n, s))) return rc;
   // block norms, needed only to compare with a positive threshold
-  std::vector<double> an, bn;
+  double *dn = nullptr;
   if (eps > 0.0) {
-    double *dn = nullptr;
     if ((rc = tmp.alloc(&dn, (size_t)(A->nnzb + B->nnzb)))) return rc;
     hipError_t e = launch_block_norms(static_cast<const double *>(A->dir[0].vals),
                                       A->dir[0].blk_pos, A->blk_row, A->col_idx, A->b, A->nnzb,
@@ -1005,60 +998,73 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
       e = launch_block_norms(static_cast<const double *>(B->dir[0].vals), B->dir[0].blk_pos,
                              B->blk_row, B->col_idx, B->b, B->nnzb, dn + A->nnzb, s);
     if (e != hipSuccess) return hip_fail(e, "block norm kernel launch");
-    if ((rc = d2h(an, dn, A->nnzb, s)) || (rc = d2h(bn, dn + A->nnzb, B->nnzb, s))) return rc;
   }
   HIP_TRY(hipStreamSynchronize(s), "spgemm");
   if (b != bb) return fail(VBCSR_EINVAL, "A and B must be over the same atoms (block sizes differ)");
   st.ms_norms = ms_since(t0);
 
-  // symbolic stage (host) and its lists on the device
+  // symbolic stage on the device
   t0 = clk::now();
-  SpgemmPlan plan;
-  spgemm_symbolic(n, b.data(), arp.data(), aci.data(), apos.data(),
-                  eps > 0.0 ? an.data() : nullptr, brp.data(), bci.data(), bpos.data(),
-                  eps > 0.0 ? bn.data() : nullptr, eps, plan);
-  const int64_t nC = (int64_t)plan.oi.size();
-  const int64_t nvals = plan.obase[nC];
-  st.candidates = plan.candidates;
-  st.kept_symbolic = nC;
-  st.products = (int64_t)plan.pa.size();
-  st.flops = plan.flops;
-  // output blocks grouped by tile class (one launch each)
-  std::vector<int32_t> order((size_t)nC);
-  int64_t cls_begin[6] = {0, 0, 0, 0, 0, 0};
-  for (int64_t c = 0; c < nC; ++c) cls_begin[spgemm_class(b[plan.oi[c]], b[plan.oj[c]]) + 1]++;
-  for (int k = 0; k < 5; ++k) cls_begin[k + 1] += cls_begin[k];
+  SymbolicIn sin{};
+  sin.n = n;
+  sin.annzb = A->nnzb;
+  sin.b = A->b;
+  sin.arp = A->row_ptr;
+  sin.aci = A->col_idx;
+  sin.arow = A->blk_row;
+  sin.apos = A->dir[1].blk_pos;
+  sin.an = eps > 0.0 ? dn : nullptr;
+  sin.brp = B->row_ptr;
+  sin.bci = B->col_idx;
+  sin.bpos = B->dir[0].blk_pos;
+  sin.bn = eps > 0.0 ? dn + A->nnzb : nullptr;
+  sin.eps = eps;
+  SymbolicOut so;
+  int alloc_rc = VBCSR_OK;
+  const DevAlloc dalloc = [&](void **q, size_t bytes) -> hipError_t {
+    char *c = nullptr;
+    alloc_rc = tmp.alloc(&c, bytes);
+    *q = c;
+    return alloc_rc == VBCSR_OK ? hipSuccess : hipErrorOutOfMemory;
+  };
   {
-    int64_t fill[5];
-    std::copy(cls_begin, cls_begin + 5, fill);
-    for (int64_t c = 0; c < nC; ++c)
-      order[fill[spgemm_class(b[plan.oi[c]], b[plan.oj[c]])]++] = (int32_t)c;
+    hipError_t e = spgemm_symbolic_device(sin, so, dalloc, s);
+    if (alloc_rc != VBCSR_OK) return alloc_rc;
+    if (e == hipErrorInvalidValue)
+      return fail(VBCSR_EUNSUPPORTED, "the block product has 2^31 or more block products");
+    if (e != hipSuccess) return hip_fail(e, "symbolic stage");
   }
+  const int64_t nC = so.nC;
+  const int64_t nvals = so.nvals;
+  st.candidates = so.candidates;
+  st.kept_symbolic = nC;
+  st.products = so.nP;
+  st.flops = so.flops;
+  // C's structure on the host (the final filter and C's plan need it)
+  std::vector<int64_t> prp, pobase;
+  std::vector<int32_t> poj;
+  if ((rc = d2h(prp, so.crp, (size_t)n + 1, s)) || (rc = d2h(poj, so.oj, (size_t)nC, s)) ||
+      (rc = d2h(pobase, so.obase, (size_t)nC + 1, s)))
+    return rc;
+  const int64_t *cls_begin = so.cls_begin;
   SpgemmParams sp{};
   sp.avals = static_cast<const double *>(A->dir[1].vals);
   sp.bvals = static_cast<const double *>(B->dir[0].vals);
   sp.b = A->b;
-
-  int32_t *d_oi = nullptr, *d_oj = nullptr, *d_order = nullptr;
-  int64_t *d_obase = nullptr, *d_pptr = nullptr, *d_pa = nullptr, *d_pb = nullptr;
   double *cvals = nullptr, *cnorm = nullptr;
-  if ((rc = tmp.up(&d_oi, plan.oi, s)) || (rc = tmp.up(&d_oj, plan.oj, s)) ||
-      (rc = tmp.up(&d_obase, plan.obase, s)) || (rc = tmp.up(&d_pptr, plan.pptr, s)) ||
-      (rc = tmp.up(&d_pa, plan.pa, s)) || (rc = tmp.up(&d_pb, plan.pb, s)) ||
-      (rc = tmp.up(&d_order, order, s)) ||
-      (rc = tmp.alloc(&cvals, (size_t)nvals)) ||
-      (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
+  if ((rc = tmp.alloc(&cvals, (size_t)nvals)) || (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
     return rc;
   HIP_TRY(hipStreamSynchronize(s), "spgemm");
   st.ms_symbolic = ms_since(t0);
-  sp.oi = d_oi;
-  sp.oj = d_oj;
-  sp.obase = d_obase;
-  sp.pptr = d_pptr;
-  sp.pa = d_pa;
-  sp.pb = d_pb;
+  sp.oi = so.oi;
+  sp.oj = so.oj;
+  sp.obase = so.obase;
+  sp.pptr = so.pptr;
+  sp.pa = so.pa;
+  sp.pb = so.pb;
   sp.cvals = cvals;
   sp.cnorm = cnorm;
+  const int32_t *d_order = so.order;
 
   // numeric stage, timed with events on the stream
   const int max_b = n ? *std::max_element(b.begin(), b.end()) : 1;
@@ -1069,7 +1075,7 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
     return fail(VBCSR_EHIP, "hipEventCreate");
   }
   hipError_t e = hipEventRecord(ev[0], s);
-  for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+  for (int k = 0; k < 5 && e == hipSuccess && nC > 0; ++k) {
     SpgemmParams pk = sp;
     pk.order = d_order + cls_begin[k];
     pk.count = cls_begin[k + 1] - cls_begin[k];
@@ -1089,8 +1095,8 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   // C's structure: the symbolic pattern, or the filtered one built below
   std::vector<int64_t> crp;
   std::vector<int32_t> ccol;
-  const int64_t *c_rp = plan.row_ptr.data();
-  const int32_t *c_ci = plan.oj.data();
+  const int64_t *c_rp = prp.data();
+  const int32_t *c_ci = poj.data();
   int64_t c_nnzb = nC;
   const double *final_vals = cvals;
   int64_t final_nvals = nvals;
@@ -1104,10 +1110,10 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
     parallel_rows(n, [&](int32_t r0, int32_t r1) {
       for (int32_t i = r0; i < r1; ++i) {
         int64_t k = 0, v = 0;
-        for (int64_t c = plan.row_ptr[i]; c < plan.row_ptr[i + 1]; ++c)
+        for (int64_t c = prp[i]; c < prp[i + 1]; ++c)
           if (!(nrm[c] < eps)) {
             ++k;
-            v += plan.obase[c + 1] - plan.obase[c];
+            v += pobase[c + 1] - pobase[c];
           }
         crp[i + 1] = k;
         vrp[i + 1] = v;
@@ -1124,12 +1130,12 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
     parallel_rows(n, [&](int32_t r0, int32_t r1) {
       for (int32_t i = r0; i < r1; ++i) {
         int64_t u = crp[i], pos = vrp[i];
-        for (int64_t c = plan.row_ptr[i]; c < plan.row_ptr[i + 1]; ++c) {
+        for (int64_t c = prp[i]; c < prp[i + 1]; ++c) {
           if (nrm[c] < eps) continue;
-          ccol[u] = plan.oj[c];
-          sbase[u] = plan.obase[c];
+          ccol[u] = poj[c];
+          sbase[u] = pobase[c];
           dbase[u] = pos;
-          size[u] = (int32_t)(plan.obase[c + 1] - plan.obase[c]);
+          size[u] = (int32_t)(pobase[c + 1] - pobase[c]);
           pos += size[u];
           ++u;
         }

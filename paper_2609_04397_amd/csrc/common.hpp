@@ -145,32 +145,6 @@ void build_plan(int32_t n, const int32_t *b, const int64_t *row_ptr, const int32
                 int32_t n_rows = -1);
 
 
-// Symbolic stage of the thresholded block product C = A B over one atom set
-// (host).  Candidates of row i are the columns j of the rows k of B with a
-// block (i, k) in A; each carries the bound U_ij = sum_k ||A_ik|| ||B_kj||
-// summed over k in A's stored order, and is kept unless U_ij < eps (with no
-// norms given every candidate is kept).  Kept columns are ascending per row.
-// The products of each kept block are listed in A's stored order of k.
-struct SpgemmPlan {
-  int64_t candidates = 0;        // distinct (i, j) reached through some k
-  std::vector<int64_t> row_ptr;  // n+1, over kept blocks
-  RawVec<int32_t> oi, oj;        // per kept block: row and column atom
-  RawVec<double> bound;          // per kept block: U_ij (0 when no norms)
-  RawVec<int64_t> obase;         // per kept block + 1: graph-order value offsets
-  RawVec<int64_t> pptr;          // per kept block + 1: product ranges
-  RawVec<int64_t> pa;            // per product: apos of A_ik << 8 | b_k
-  RawVec<int64_t> pb;            // per product: bpos of B_kj
-  double flops = 0.0;            // sum over products of 2 b_i b_k b_j
-};
-
-// apos / bpos: page offset of every graph block of A and of B (the device
-// reads A_ik row-major from A's transposed pages and B_kj column-major from
-// B's forward pages).  an / bn: block norms, or both null.
-void spgemm_symbolic(int32_t n, const int32_t *b, const int64_t *arp, const int32_t *aci,
-                     const int64_t *apos, const double *an, const int64_t *brp,
-                     const int32_t *bci, const int64_t *bpos, const double *bn, double eps,
-                     SpgemmPlan &out);
-
 // Record `msg` as the calling thread's last error (read by vbcsr_last_error)
 // and return `code`.
 int set_error(int code, const std::string &msg);

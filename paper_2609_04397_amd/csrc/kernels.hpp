@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 
 #include "common.hpp"
 
@@ -127,6 +128,46 @@ inline int spgemm_class(int bi, int bj) {
   return ti > 2 || tj > 2 ? 4 : (ti - 1) * 2 + (tj - 1);
 }
 hipError_t launch_spgemm_numeric(const SpgemmParams &p, int cls, int max_b, hipStream_t s);
+
+// Symbolic stage of C = A B on the device (symbolic.hip).  Inputs are device
+// arrays of the two handles: A's graph (row pointer arp, columns aci, row of
+// every block arow), the page offset of every block of A in A's transposed
+// pages (apos) and of B in B's forward pages (bpos), block sizes b, and the
+// block norms an / bn (both null: every candidate is kept).  A candidate
+// (i, j) is kept unless its bound sum_k ||A_ik|| ||B_kj||, summed over k in
+// A's stored order, is below eps.  Outputs (device, allocated through
+// `alloc`, which the caller frees): per kept block, in row order and with
+// columns ascending, oi / oj / bound, obase and pptr (nC + 1 entries: value
+// offsets in graph order, product ranges), C's row pointer crp (n + 1), the
+// products pa (apos << 8 | b_k) / pb (bpos) in A's stored order of k, and
+// the blocks grouped by tile class (order, stable; class k holds
+// order[cls_begin[k] .. cls_begin[k+1])).
+using DevAlloc = std::function<hipError_t(void **, size_t)>;
+struct SymbolicIn {
+  int32_t n;
+  int64_t annzb;
+  const int32_t *b;
+  const int64_t *arp;
+  const int32_t *aci, *arow;
+  const int64_t *apos;
+  const double *an;
+  const int64_t *brp;
+  const int32_t *bci;
+  const int64_t *bpos;
+  const double *bn;
+  double eps;
+};
+struct SymbolicOut {
+  int32_t *oi = nullptr, *oj = nullptr, *order = nullptr;
+  int64_t *obase = nullptr, *pptr = nullptr, *pa = nullptr, *pb = nullptr, *crp = nullptr;
+  double *bound = nullptr;
+  int64_t nC = 0, nP = 0, nvals = 0, candidates = 0, products_all = 0;
+  double flops = 0.0;
+  int64_t cls_begin[6] = {0, 0, 0, 0, 0, 0};
+};
+// hipErrorInvalidValue when the product has 2^31 or more candidate products
+hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const DevAlloc &alloc,
+                                  hipStream_t s);
 
 // out[k] = Frobenius norm of graph block k, read from forward pages at pos[k].
 hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,

@@ -114,23 +114,6 @@ int main() {
     CHECK(validate_graph(g.n, g.b.data(), g.rp.data(), g.ci.data(), g.nval + 1, err) ==
           VBCSR_ESHAPE);
   }
-  // block-product symbolic stage with and without norms
-  {
-    Graph g = random_graph(9000, 6, 5, true);
-    HostPlan p;
-    build_plan(g.n, g.b.data(), g.rp.data(), g.ci.data(), VBCSR_ORDER_ATOM, p, false);
-    std::vector<double> nrm((size_t)g.ci.size());
-    std::mt19937_64 rng(3);
-    for (auto &x : nrm) x = (double)(rng() % 1000) / 100.0;
-    for (double eps : {0.0, 5.0}) {
-      SpgemmPlan sp;
-      spgemm_symbolic(g.n, g.b.data(), g.rp.data(), g.ci.data(), p.tr.blk_pos.data(),
-                      eps > 0 ? nrm.data() : nullptr, g.rp.data(), g.ci.data(),
-                      p.fwd.blk_pos.data(), eps > 0 ? nrm.data() : nullptr, eps, sp);
-      CHECK(sp.row_ptr.size() == (size_t)g.n + 1);
-      CHECK((int64_t)sp.oi.size() == sp.row_ptr[g.n]);
-    }
-  }
   // halo plans of an 8-rank split of a random graph
   {
     Graph g = random_graph(6000, 6, 9, true);

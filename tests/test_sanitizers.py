@@ -1,8 +1,7 @@
 """Host code under the sanitizers (CPU build, no GPU).
 
 The library's host stages (validation, planner in every order including the
-threaded paths, rank-local plans, the block product's symbolic stage, halo
-plans) run under AddressSanitizer + UndefinedBehaviorSanitizer and under
+threaded paths, rank-local plans, halo plans) run under AddressSanitizer + UndefinedBehaviorSanitizer and under
 ThreadSanitizer; the CPU oracle runs under AddressSanitizer +
 UndefinedBehaviorSanitizer (its OpenMP runtime is not instrumented for
 ThreadSanitizer).  Built with g++/gcc from the sources; no device code.
@@ -16,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SAN = os.path.join(ROOT, "tests", "sanitize")
 CSRC = os.path.join(ROOT, "paper_2609_04397_amd", "csrc")
-HOST_SOURCES = [os.path.join(CSRC, f) for f in ("planner.cpp", "spgemm.cpp", "halo.cpp")]
+HOST_SOURCES = [os.path.join(CSRC, f) for f in ("planner.cpp", "halo.cpp")]
 
 pytestmark = pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
 
