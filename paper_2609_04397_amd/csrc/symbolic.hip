@@ -212,12 +212,28 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   out = SymbolicOut{};
   const int32_t n = in.n;
   const int64_t annzb = in.annzb;
+  // arrays are carved out of a few large allocations (one per phase):
+  // device allocations and frees cost about as much per call as per byte
+  struct Arena {
+    char *base = nullptr;
+    size_t size = 0, used = 0;
+  } arena;
+  auto reserve = [&](size_t bytes) -> hipError_t {
+    void *q = nullptr;
+    hipError_t e = alloc(&q, bytes + 256);
+    arena.base = static_cast<char *>(q);
+    arena.size = bytes + 256;
+    arena.used = 0;
+    return e;
+  };
+  auto sz = [](size_t elem, size_t count) { return (elem * (count ? count : 1) + 255) / 256 * 256; };
   auto get = [&](auto **p, size_t count) -> hipError_t {
     using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
-    void *q = nullptr;
-    hipError_t e = alloc(&q, sizeof(T) * (count ? count : 1));
-    *p = static_cast<T *>(q);
-    return e;
+    const size_t bytes = sz(sizeof(T), count);
+    if (arena.used + bytes > arena.size) return hipErrorOutOfMemory;  // sizes below are exact
+    *p = reinterpret_cast<T *>(arena.base + arena.used);
+    arena.used += bytes;
+    return hipSuccess;
   };
   auto fetch = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
     SYM_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
@@ -238,6 +254,7 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
 
   // entries per stored block of A and their offsets
   int64_t *cnt = nullptr, *eoff = nullptr, *seg = nullptr;
+  SYM_TRY(reserve(2 * sz(8, (size_t)annzb + 1) + sz(8, (size_t)n + 1)));
   SYM_TRY(get(&cnt, (size_t)annzb + 1));
   SYM_TRY(get(&eoff, (size_t)annzb + 1));
   SYM_TRY(get(&seg, (size_t)n + 1));
@@ -253,6 +270,7 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   if (nE >= (int64_t(1) << 31)) return hipErrorInvalidValue;  // beyond the 32-bit sort counts
   out.products_all = nE;
   if (nE == 0) {
+    SYM_TRY(reserve(sz(8, (size_t)n + 1) + 2 * sz(8, 1)));
     SYM_TRY(get(&out.crp, (size_t)n + 1));
     SYM_TRY(hipMemsetAsync(out.crp, 0, sizeof(int64_t) * ((size_t)n + 1), s));
     SYM_TRY(get(&out.pptr, 1));
@@ -265,6 +283,8 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   // expand and sort per row by (j, position of A_ik in the row)
   uint64_t *key = nullptr, *key_s = nullptr;
   int64_t *val = nullptr, *val_s = nullptr;
+  int32_t *flag = nullptr, *ginc = nullptr;
+  SYM_TRY(reserve(4 * sz(8, (size_t)nE) + 2 * sz(4, (size_t)nE)));
   SYM_TRY(get(&key, (size_t)nE));
   SYM_TRY(get(&key_s, (size_t)nE));
   SYM_TRY(get(&val, (size_t)nE));
@@ -279,7 +299,6 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   }));
 
   // candidates: runs of equal j
-  int32_t *flag = nullptr, *ginc = nullptr;
   SYM_TRY(get(&flag, (size_t)nE));
   SYM_TRY(get(&ginc, (size_t)nE));
   const dim3 rows_grid((unsigned)((n + 3) / 4));
@@ -294,6 +313,8 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   out.candidates = nG;
   int64_t *gstart = nullptr;
   int32_t *grow = nullptr, *gj = nullptr;
+  SYM_TRY(reserve(sz(8, (size_t)nG) + 2 * sz(4, (size_t)nG) + 6 * sz(8, (size_t)nG + 1) +
+                  2 * sz(8, (size_t)nG) + sz(8, 1)));
   SYM_TRY(get(&gstart, (size_t)nG));
   SYM_TRY(get(&grow, (size_t)nG));
   SYM_TRY(get(&gj, (size_t)nG));
@@ -342,7 +363,10 @@ hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const 
   out.nP = tot[1];
   out.nvals = tot[2];
 
-  // C's blocks, row pointer and product lists
+  // C's blocks, row pointer and product lists (and the class sort)
+  SYM_TRY(reserve(2 * sz(4, (size_t)nC) + sz(8, (size_t)nC) + 2 * sz(8, (size_t)nC + 1) +
+                  sz(8, (size_t)n + 1) + 2 * sz(8, (size_t)out.nP) + 2 * sz(4, (size_t)nC) +
+                  2 * sz(4, (size_t)nC) + sz(4, 5)));
   SYM_TRY(get(&out.oi, (size_t)nC));
   SYM_TRY(get(&out.oj, (size_t)nC));
   SYM_TRY(get(&out.bound, (size_t)nC));
