@@ -1385,7 +1385,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_lds(SddmmParams<T> P) {
 // rows with one 16-byte load (rows past the panel are not loaded).  Column indices and output maps are loaded two tiles ahead.
 // Requires X within 2^31 bytes (one buffer descriptor).
 template <int NCH>
-__global__ void __launch_bounds__(kThreads) k_sddmm_dma(SddmmParams<double> P) {
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sddmm_dma(SddmmParams<double> P) {
   using LdsPtr = __attribute__((address_space(3))) void *;
   constexpr int CW = 32;
   __shared__ __align__(16) double xs_all[kWaves * 16 * CW];
@@ -1444,10 +1444,11 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_dma(SddmmParams<double> P) {
     // tile j); they move along at the start of a tile, after the step's wait,
     // so no copy waits on a load in flight
     v4u32 xr_cur = rows_of(0), xr_nxt = rows_of(1), xr_nn = xr_nxt;
-    int64_t g_cur = gmap_of(0), g_nxt = gmap_of(1), g_nn = g_nxt, g_done = 0;
+    int64_t g_cur = gmap_of(0), g_nxt = gmap_of(1), g_nn = g_nxt, g_done = 0, g_carry = 0;
     issue(0, xr_cur);
     v4d acc0 = v4d{}, acc1 = v4d{};
-    double done[4] = {0.0, 0.0, 0.0, 0.0};
+    double done[4] = {0.0, 0.0, 0.0, 0.0}, carry[4] = {0.0, 0.0, 0.0, 0.0};
+    int csplit = 16;   // lanes m >= csplit hold carried outputs of the tile before
     for (int j = 0; j < ntiles; ++j) {
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) {
@@ -1476,14 +1477,41 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_dma(SddmmParams<double> P) {
         if (ch == 0) {
           xr_nn = rows_of(j + 2);
           g_nn = gmap_of(j + 2);
-          if (j > 0 && (j - 1) * 16 + m < K) {   // outputs of tile j - 1
-            const int64_t base = g_done >> 7;
-            const int bj = (int)(g_done & 127);
+          if (j > 0) {
+            // Outputs of tile j - 1 (a whole tile: j - 1 is not the last).
+            // A block whose columns run on into tile j is held back and
+            // stored with the rest of it after tile j, so that each block's
+            // lines are written in one burst.  split = first column of that
+            // block in tile j - 1 (16: none held back).
+            const uint32_t u = (uint32_t)(g_done >> 7);
+            const uint32_t up = __shfl(u, lane - 1, 64);
+            const bool brk = m == 0 || u != up + 1u;
+            const uint32_t u15 = __shfl(u, 15, 64);
+            const uint32_t unext = (uint32_t)(__shfl(g_cur, 0, 64) >> 7);
+            const uint32_t brks = (uint32_t)__ballot(brk) & 0xFFFFu;
+            const int split = unext == u15 + 1u ? 31 - __builtin_clz(brks) : 16;
+            if (m >= csplit) {
+              const int64_t base = g_carry >> 7;
+              const int bj = (int)(g_carry & 127);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const int pr = mt * 16 + dst_row<double>(kq, i);
-              if (pr < b) P.dA[base + (int64_t)pr * bj] = done[i];
+              for (int i = 0; i < 4; ++i) {
+                const int pr = mt * 16 + dst_row<double>(kq, i);
+                if (pr < b) P.dA[base + (int64_t)pr * bj] = carry[i];
+              }
             }
+            if (m < split) {
+              const int64_t base = g_done >> 7;
+              const int bj = (int)(g_done & 127);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int pr = mt * 16 + dst_row<double>(kq, i);
+                if (pr < b) P.dA[base + (int64_t)pr * bj] = done[i];
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) carry[i] = done[i];
+            g_carry = g_done;
+            csplit = split;
           }
         }
 #pragma unroll
@@ -1493,7 +1521,16 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_dma(SddmmParams<double> P) {
         }
       }
     }
-    // outputs of the last tile
+    // held-back outputs of the tile before the last, then the last tile
+    if (m >= csplit) {
+      const int64_t base = g_carry >> 7;
+      const int bj = (int)(g_carry & 127);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pr = mt * 16 + dst_row<double>(kq, i);
+        if (pr < b) P.dA[base + (int64_t)pr * bj] = carry[i];
+      }
+    }
     if ((ntiles - 1) * 16 + m < K) {
       const int64_t base = g_cur >> 7;
       const int bj = (int)(g_cur & 127);
