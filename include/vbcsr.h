@@ -358,10 +358,11 @@ typedef struct {
   int64_t products;      /* block products A_ik B_kj evaluated                   */
   double flops;          /* sum over evaluated products of 2 b_i b_k b_j         */
   double ms_norms;       /* block sizes copy-back and block norms of A and B    */
-  double ms_symbolic;    /* device symbolic stage, C's pattern back to the host */
+  double ms_symbolic;    /* device symbolic stage (and C's pattern back to the
+                            host when the filter or C's row order needs it)      */
   double ms_numeric;     /* numeric kernel (device events around it)            */
   double ms_filter;      /* final filter: norms back and compaction             */
-  double ms_build;       /* planning and packing of C                           */
+  double ms_build;       /* planning (device or host) and packing of C          */
 } vbcsr_spgemm_stats;
 
 /*
@@ -378,13 +379,18 @@ typedef struct {
  *      A_ik B_kj of the block in A's stored order of k, on matrix cores, FP64;
  *   4. final filter: computed blocks whose Frobenius norm is below eps are
  *      removed (nothing is removed at eps = 0);
- *   5. C is planned and packed like a vbcsr_create result.
+ *   5. C is laid out and packed like a vbcsr_create result.  With row order
+ *      VBCSR_ORDER_AUTO (or opts NULL) C's panels are processed in A's
+ *      processing order, with VBCSR_ORDER_ATOM in atom order; both layouts
+ *      are computed on the device from the pattern already there.  RCM and
+ *      cluster orders of C's own graph are computed by the host planner.
+ *      The order changes no result of any product with C.
  *   out     receives the new FP64 handle C over the same atoms (NULL on failure)
  *   A, B    FP64 handles over the same atoms (same block sizes)
  *   eps     block-norm threshold, >= 0
  *   opts    planner options of C (may be NULL)
  *   stats   may be NULL
- * Synchronises `stream` (C's pattern is planned on the host).
+ * Synchronises `stream`.
  * Errors: EINVAL (null arguments, different atoms, eps < 0 or NaN, bad
  * options), EUNSUPPORTED (non-FP64 handles, 2^31 or more candidate block
  * products, or C outside vbcsr_create's limits), ENOMEM, EHIP.

@@ -20,7 +20,7 @@ OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvbcsr.so")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "abi.cpp", "planner.cpp", "symbolic.hip", "zkernels.hip", "zmat.cpp",
+SOURCES = ["kernels.hip", "abi.cpp", "planner.cpp", "symbolic.hip", "plan_device.hip", "zkernels.hip", "zmat.cpp",
            "halo.cpp"]
 
 # Packed FP32 instructions are disabled for every device compile.  Matrix-core

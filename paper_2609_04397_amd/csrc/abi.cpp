@@ -329,6 +329,53 @@ int plan_checked(int32_t n, const int32_t *b, const int64_t *row_ptr, const int3
   return VBCSR_OK;
 }
 
+// Column tables and zeroed value pages of direction d, once its panel
+// descriptors, per-block maps (and BF16 panel bases) are on the device.
+int finish_direction(vbcsr_mat *A, int d, int64_t n_cols, hipStream_t s) {
+  DevDir &D = A->dir[d];
+  int rc;
+  // 4 entries of slack: a kernel may read a panel's indices in groups of
+  // four (never using those past the panel)
+  if ((rc = alloc_into(A, &D.colx, (size_t)n_cols + 4))) return rc;
+  if (d == 0 && (rc = alloc_into(A, &D.colg, (size_t)n_cols))) return rc;
+  {
+    ColumnParams cp{};
+    cp.rows = D.rows;
+    cp.prow = D.blk_prow;
+    cp.k0 = D.blk_k0;
+    cp.catom = d == 0 ? A->col_idx : A->blk_row;
+    cp.b = A->b;
+    cp.off = A->off;
+    cp.gbase = d == 0 ? A->gbase : nullptr;
+    cp.nnzb = A->nnzb;
+    cp.colx = D.colx;
+    cp.colg = d == 0 ? D.colg : nullptr;
+    hipError_t e = launch_columns(cp, s);
+    if (e != hipSuccess) return hip_fail(e, "column table kernel launch");
+  }
+  if (A->prec == VBCSR_BF16X3) {
+    if ((rc = alloc_into(A, &D.hi, (size_t)D.n_values16))) return rc;
+    if ((rc = alloc_into(A, &D.lo, (size_t)D.n_values16))) return rc;
+    if (D.n_values16) {
+      hipError_t e = hipMemsetAsync(D.hi, 0, sizeof(uint16_t) * D.n_values16, s);
+      if (e == hipSuccess) e = hipMemsetAsync(D.lo, 0, sizeof(uint16_t) * D.n_values16, s);
+      if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    }
+  } else {
+    const size_t es = A->prec == VBCSR_FP64 ? 8 : 4;
+    char *p = nullptr;
+    // kPageSlack values after the pages: 16-byte reads that start on a
+    // block's last value stay inside the allocation
+    const size_t bytes = es * (size_t)(D.n_values + kPageSlack);
+    if ((rc = alloc_into(A, &p, bytes))) return rc;
+    // the padding after each panel must read as zero
+    hipError_t e = hipMemsetAsync(p, 0, bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    D.vals = p;
+  }
+  return VBCSR_OK;
+}
+
 // Shared by vbcsr_create (host values) and the block product (device values
 // in graph order).
 int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
@@ -386,49 +433,11 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
     D.n_values16 = P.n_values16;
     D.npanels = (int32_t)P.rows.size();
     if ((rc = upload_into(A, &D.rows, P.rows, s))) return bail(rc);
-    // 4 entries of slack: a kernel may read a panel's indices in groups of
-    // four (never using those past the panel)
-    if ((rc = alloc_into(A, &D.colx, (size_t)P.n_cols + 4))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_pos, P.blk_pos, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_k0, P.blk_k0, s))) return bail(rc);
     if ((rc = upload_into(A, &D.blk_prow, P.blk_prow, s))) return bail(rc);
-    if (d == 0 && (rc = alloc_into(A, &D.colg, (size_t)P.n_cols))) return bail(rc);
-    {
-      ColumnParams cp{};
-      cp.rows = D.rows;
-      cp.prow = D.blk_prow;
-      cp.k0 = D.blk_k0;
-      cp.catom = d == 0 ? A->col_idx : A->blk_row;
-      cp.b = A->b;
-      cp.off = A->off;
-      cp.gbase = d == 0 ? A->gbase : nullptr;
-      cp.nnzb = A->nnzb;
-      cp.colx = D.colx;
-      cp.colg = d == 0 ? D.colg : nullptr;
-      hipError_t e = launch_columns(cp, s);
-      if (e != hipSuccess) return bail(hip_fail(e, "column table kernel launch"));
-    }
-    if (prec == VBCSR_BF16X3) {
-      if ((rc = upload_into(A, &D.vbase16, P.vbase16, s))) return bail(rc);
-      if ((rc = alloc_into(A, &D.hi, (size_t)P.n_values16))) return bail(rc);
-      if ((rc = alloc_into(A, &D.lo, (size_t)P.n_values16))) return bail(rc);
-      if (P.n_values16) {
-        hipError_t e = hipMemsetAsync(D.hi, 0, sizeof(uint16_t) * P.n_values16, s);
-        if (e == hipSuccess) e = hipMemsetAsync(D.lo, 0, sizeof(uint16_t) * P.n_values16, s);
-        if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
-      }
-    } else {
-      const size_t es = prec == VBCSR_FP64 ? 8 : 4;
-      char *p = nullptr;
-      // kPageSlack values after the pages: 16-byte reads that start on a
-      // block's last value stay inside the allocation
-      const size_t bytes = es * (size_t)(P.n_values + kPageSlack);
-      if ((rc = alloc_into(A, &p, bytes))) return bail(rc);
-      // the padding after each panel must read as zero
-      hipError_t e = hipMemsetAsync(p, 0, bytes, s);
-      if (e != hipSuccess) return bail(hip_fail(e, "hipMemsetAsync"));
-      D.vals = p;
-    }
+    if (prec == VBCSR_BF16X3 && (rc = upload_into(A, &D.vbase16, P.vbase16, s))) return bail(rc);
+    if ((rc = finish_direction(A, d, P.n_cols, s))) return bail(rc);
   }
   // initial values: host graph order -> device staging -> pages
   if (plan.nnz > 0 && values_on_device) {
@@ -455,6 +464,92 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
   }
   *out = A;
   A = nullptr;  // owned by the caller now
+  return VBCSR_OK;
+}
+
+// An FP64 operator over A's atoms whose block graph is already on the device
+// (row pointer d_rp, n + 1 entries; columns d_ci, ascending within each row)
+// with graph-order values d_vals (n_values of them): planned on the device in
+// the processing order d_order (a permutation of the atoms), so the pattern
+// never passes through the host.
+int create_planned_on_device(vbcsr_mat **out, const vbcsr_mat *A, int64_t nnzb, int64_t n_values,
+                             const int64_t *d_rp, const int32_t *d_ci, const double *d_vals,
+                             const int32_t *d_order, const vbcsr_plan_opts *opts,
+                             const DevAlloc &tmp_alloc, hipStream_t s) {
+  *out = nullptr;
+  vbcsr_mat *C = new vbcsr_mat();
+  struct Guard {
+    vbcsr_mat *&h;
+    ~Guard() {
+      if (h) {
+        free_all(h);
+        delete h;
+      }
+    }
+  } guard{C};
+  const int32_t n = A->n;
+  C->n = n;
+  C->n_rows = n;
+  C->N = A->N;
+  C->N_rows = A->N;
+  C->nnzb = nnzb;
+  C->prec = VBCSR_FP64;
+  if (opts) C->opts = *opts;
+  int rc;
+  if ((rc = alloc_into(C, &C->b, (size_t)n)) || (rc = alloc_into(C, &C->off, (size_t)n)) ||
+      (rc = alloc_into(C, &C->row_ptr, (size_t)n + 1)) ||
+      (rc = alloc_into(C, &C->col_idx, (size_t)nnzb)) ||
+      (rc = alloc_into(C, &C->blk_row, (size_t)nnzb)) ||
+      (rc = alloc_into(C, &C->gbase, (size_t)nnzb + 1)))
+    return rc;
+  HIP_TRY(hipMemcpyAsync(C->b, A->b, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(C->off, A->off, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s),
+          "hipMemcpyAsync");
+  HIP_TRY(hipMemcpyAsync(C->row_ptr, d_rp, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s),
+          "hipMemcpyAsync");
+  if (nnzb)
+    HIP_TRY(hipMemcpyAsync(C->col_idx, d_ci, sizeof(int32_t) * nnzb, hipMemcpyDeviceToDevice, s),
+            "hipMemcpyAsync");
+  DevPlanIn pin{n, nnzb, C->b, C->off, C->row_ptr, C->col_idx, d_order};
+  DevPlanOut po{};
+  po.blk_row = C->blk_row;
+  po.gbase = C->gbase;
+  for (int d = 0; d < 2; ++d) {
+    DevDir &D = C->dir[d];
+    if ((rc = alloc_into(C, &D.rows, (size_t)n)) || (rc = alloc_into(C, &D.blk_pos, (size_t)nnzb)) ||
+        (rc = alloc_into(C, &D.blk_k0, (size_t)nnzb)) ||
+        (rc = alloc_into(C, &D.blk_prow, (size_t)nnzb)))
+      return rc;
+    po.dir[d].rows = D.rows;
+    po.dir[d].blk_pos = D.blk_pos;
+    po.dir[d].blk_k0 = D.blk_k0;
+    po.dir[d].blk_prow = D.blk_prow;
+  }
+  {
+    hipError_t e = plan_device(pin, po, tmp_alloc, s);
+    if (e == hipErrorInvalidValue) return fail(VBCSR_EUNSUPPORTED, "the product has 2^31 or more blocks");
+    if (e != hipSuccess) return hip_fail(e, "device plan");
+  }
+  if (po.nnz != n_values) return fail(VBCSR_ESHAPE, "product values do not match its pattern");
+  // the same limit as validate_graph: one panel within 2^31 bytes in FP64
+  constexpr int64_t kPanelMax = (int64_t(1) << 31) / 8;
+  if (po.dir[0].max_panel >= kPanelMax)
+    return fail(VBCSR_EUNSUPPORTED, "a block row of the product holds 2^28 or more values");
+  if (po.dir[1].max_panel >= kPanelMax)
+    return fail(VBCSR_EUNSUPPORTED, "a block column of the product holds 2^28 or more values");
+  C->nnz = po.nnz;
+  C->n_shapes = po.n_shapes;
+  for (int d = 0; d < 2; ++d) {
+    DevDir &D = C->dir[d];
+    D.n_values = po.dir[d].n_values;
+    D.n_values16 = 0;
+    D.npanels = n;
+    if ((rc = finish_direction(C, d, po.dir[d].n_cols, s))) return rc;
+  }
+  if (C->nnz > 0 && (rc = pack_all(C, d_vals, 0, s))) return rc;
+  HIP_TRY(hipStreamSynchronize(s), "spgemm");
+  *out = C;
+  C = nullptr;  // owned by the caller now
   return VBCSR_OK;
 }
 
@@ -1040,12 +1135,19 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   st.kept_symbolic = nC;
   st.products = so.nP;
   st.flops = so.flops;
-  // C's structure on the host (the final filter and C's plan need it)
+  // C is planned on the device in A's processing order (row order AUTO) or
+  // in atom order; an RCM or cluster order of C's own graph is computed by
+  // the host planner.  C's structure goes to the host only for that and for
+  // the final filter.
+  const int32_t c_order = opts ? opts->row_order : VBCSR_ORDER_AUTO;
+  const bool plan_on_device = c_order == VBCSR_ORDER_AUTO || c_order == VBCSR_ORDER_ATOM;
   std::vector<int64_t> prp, pobase;
   std::vector<int32_t> poj;
-  if ((rc = d2h(prp, so.crp, (size_t)n + 1, s)) || (rc = d2h(poj, so.oj, (size_t)nC, s)) ||
-      (rc = d2h(pobase, so.obase, (size_t)nC + 1, s)))
-    return rc;
+  if (eps > 0.0 || !plan_on_device) {
+    if ((rc = d2h(prp, so.crp, (size_t)n + 1, s)) || (rc = d2h(poj, so.oj, (size_t)nC, s)) ||
+        (rc = d2h(pobase, so.obase, (size_t)nC + 1, s)))
+      return rc;
+  }
   const int64_t *cls_begin = so.cls_begin;
   SpgemmParams sp{};
   sp.avals = static_cast<const double *>(A->dir[1].vals);
@@ -1165,8 +1267,29 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   t0 = clk::now();
   vbcsr_plan_opts copts{};
   if (opts) copts = *opts;
-  rc = create_impl(out, n, b.data(), c_rp, c_nnzb ? c_ci : nullptr, final_vals, true, final_nvals,
-                   VBCSR_FP64, &copts, stream);
+  if (plan_on_device) {
+    const int64_t *d_rp = so.crp;
+    const int32_t *d_ci = so.oj;
+    if (c_nnzb < nC) {   // the filtered pattern, from the host
+      int64_t *up_rp = nullptr;
+      int32_t *up_ci = nullptr;
+      if ((rc = tmp.up(&up_rp, crp, s)) || (rc = tmp.up(&up_ci, ccol, s))) return rc;
+      d_rp = up_rp;
+      d_ci = up_ci;
+    }
+    int32_t *d_ord = nullptr;
+    if ((rc = tmp.alloc(&d_ord, (size_t)std::max<int32_t>(n, 1)))) return rc;
+    e = c_order == VBCSR_ORDER_ATOM
+            ? launch_iota(n, d_ord, s)
+            : launch_order_from_rows(A->dir[0].rows, A->dir[0].npanels, A->off, n, d_ord, s);
+    if (e != hipSuccess) return hip_fail(e, "order kernel launch");
+    rc = create_planned_on_device(out, A, c_nnzb, final_nvals, d_rp, d_ci, final_vals, d_ord,
+                                  &copts, dalloc, s);
+    if (alloc_rc != VBCSR_OK) return alloc_rc;
+  } else {
+    rc = create_impl(out, n, b.data(), c_rp, c_nnzb ? c_ci : nullptr, final_vals, true,
+                     final_nvals, VBCSR_FP64, &copts, stream);
+  }
   if (rc) return rc;
   st.ms_build = ms_since(t0);
   if (stats) *stats = st;

@@ -169,6 +169,42 @@ struct SymbolicOut {
 hipError_t spgemm_symbolic_device(const SymbolicIn &in, SymbolicOut &out, const DevAlloc &alloc,
                                   hipStream_t s);
 
+// Plan of an operator whose block graph is on the device (both directions,
+// panels in the processing order `order`, a permutation of the n atoms):
+// the per-block maps, panel descriptors, graph value offsets (gbase, nnzb + 1
+// entries) and block rows that the host planner computes for the same order,
+// and on the host the column-table and page sizes, the largest panel (values,
+// before the alignment padding), the value count and
+// the number of (b_i, b_j) shape classes.  Columns must be ascending within
+// each row.  hipErrorInvalidValue for 2^31 or more blocks.
+struct DevPlanIn {
+  int32_t n;
+  int64_t nnzb;
+  const int32_t *b, *off;   // block sizes, first scalar rows (n entries)
+  const int64_t *rp;        // row pointer (n + 1)
+  const int32_t *ci;        // block columns (nnzb)
+  const int32_t *order;     // processing order (n)
+};
+struct DevPlanDir {
+  RowDesc *rows;            // n (device, written)
+  int64_t *blk_pos;         // nnzb (device, written)
+  int32_t *blk_k0, *blk_prow;
+  int64_t n_values = 0, n_cols = 0, max_panel = 0;
+};
+struct DevPlanOut {
+  int32_t *blk_row;         // nnzb (device, written)
+  int64_t *gbase;           // nnzb + 1 (device, written)
+  DevPlanDir dir[2];        // 0 = forward, 1 = transposed
+  int64_t nnz = 0;
+  int32_t n_shapes = 0;
+};
+hipError_t plan_device(const DevPlanIn &in, DevPlanOut &out, const DevAlloc &alloc, hipStream_t s);
+// order[p] = the atom whose first scalar row is rows[p].yrow (off ascending,
+// n entries): the processing order of an existing plan.
+hipError_t launch_order_from_rows(const RowDesc *rows, int32_t np, const int32_t *off, int32_t n,
+                                  int32_t *order, hipStream_t s);
+hipError_t launch_iota(int32_t n, int32_t *order, hipStream_t s);
+
 // out[k] = Frobenius norm of graph block k, read from forward pages at pos[k].
 hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,
                               const int32_t *col_idx, const int32_t *b, int64_t nnzb, double *out,

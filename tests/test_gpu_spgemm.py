@@ -230,6 +230,31 @@ def test_spgemm_result_planned_in_rcm_order():
     compare(op, op, 0.0, C2, C2.values().cpu().numpy())
 
 
+@pytest.mark.parametrize("eps", [0.0, 0.05])
+def test_spgemm_device_plan_matches_host_plan(eps):
+    """C laid out on the device (row orders auto and atom) and by the host
+    planner (rcm, cluster): the same operator, so its info, values, forward,
+    adjoint and block-sampled products agree bit for bit (each panel sums its
+    blocks in the same order whatever the processing order)."""
+    print("case spgemm device plan", eps, flush=True)
+    op = make_operator("C5", 0.01)
+    A = Matrix.from_operator(op)
+    Cs = {o: A.spgemm(A, eps, row_order=o)[0] for o in ("auto", "atom", "rcm", "cluster")}
+    ref = Cs["rcm"]
+    rng = np.random.default_rng(4)
+    X = torch.from_numpy(rng.standard_normal((op.N, 9))).cuda()
+    G = torch.from_numpy(rng.standard_normal((op.N, 9))).cuda()
+    want = (ref.spmm(X), ref.spmm(X, transpose=True), ref.sddmm(G, X))
+    for o, C in Cs.items():
+        assert C.info() == ref.info(), o
+        assert np.array_equal(C.row_ptr, ref.row_ptr) and np.array_equal(C.col_idx, ref.col_idx), o
+        assert torch.equal(C.values(), ref.values()), o
+        got = (C.spmm(X), C.spmm(X, transpose=True), C.sddmm(G, X))
+        for g, w in zip(got, want):
+            assert torch.equal(g, w), o
+    compare(op, op, eps, Cs["auto"], Cs["auto"].values().cpu().numpy())
+
+
 def _wide_sparse(seed, n, per, bset, b=None):
     """``per`` random columns in each of ``n`` rows (ascending): rows of the
     product have few candidates spread over many atoms."""
