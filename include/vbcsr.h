@@ -358,10 +358,9 @@ typedef struct {
   int64_t products;      /* block products A_ik B_kj evaluated                   */
   double flops;          /* sum over evaluated products of 2 b_i b_k b_j         */
   double ms_norms;       /* block sizes copy-back and block norms of A and B    */
-  double ms_symbolic;    /* device symbolic stage (and C's pattern back to the
-                            host when the filter or C's row order needs it)      */
+  double ms_symbolic;    /* device symbolic stage                               */
   double ms_numeric;     /* numeric kernel (device events around it)            */
-  double ms_filter;      /* final filter: norms back and compaction             */
+  double ms_filter;      /* final filter (device compaction)                    */
   double ms_build;       /* planning (device or host) and packing of C          */
 } vbcsr_spgemm_stats;
 
@@ -377,13 +376,14 @@ typedef struct {
  *      are ascending in every row of C;
  *   3. numeric stage on the device, one wave per output block: the products
  *      A_ik B_kj of the block in A's stored order of k, on matrix cores, FP64;
- *   4. final filter: computed blocks whose Frobenius norm is below eps are
- *      removed (nothing is removed at eps = 0);
+ *   4. final filter on the device: computed blocks whose Frobenius norm is
+ *      below eps are removed (nothing is removed at eps = 0);
  *   5. C is laid out and packed like a vbcsr_create result.  With row order
  *      VBCSR_ORDER_AUTO (or opts NULL) C's panels are processed in A's
  *      processing order, with VBCSR_ORDER_ATOM in atom order; both layouts
  *      are computed on the device from the pattern already there.  RCM and
- *      cluster orders of C's own graph are computed by the host planner.
+ *      cluster orders of C's own graph are computed by the host planner
+ *      (C's pattern is then copied back).
  *      The order changes no result of any product with C.
  *   out     receives the new FP64 handle C over the same atoms (NULL on failure)
  *   A, B    FP64 handles over the same atoms (same block sizes)

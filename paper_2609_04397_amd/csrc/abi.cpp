@@ -368,9 +368,10 @@ int finish_direction(vbcsr_mat *A, int d, int64_t n_cols, hipStream_t s) {
     // block's last value stay inside the allocation
     const size_t bytes = es * (size_t)(D.n_values + kPageSlack);
     if ((rc = alloc_into(A, &p, bytes))) return rc;
-    // the padding after each panel must read as zero
-    hipError_t e = hipMemsetAsync(p, 0, bytes, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync");
+    // the padding after each panel must read as zero; every value position
+    // is written by the packing that follows
+    hipError_t e = launch_zero_gaps(D.rows, D.npanels, D.n_values, (int)es, p, s);
+    if (e != hipSuccess) return hip_fail(e, "gap kernel launch");
     D.vals = p;
   }
   return VBCSR_OK;
@@ -1135,19 +1136,6 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   st.kept_symbolic = nC;
   st.products = so.nP;
   st.flops = so.flops;
-  // C is planned on the device in A's processing order (row order AUTO) or
-  // in atom order; an RCM or cluster order of C's own graph is computed by
-  // the host planner.  C's structure goes to the host only for that and for
-  // the final filter.
-  const int32_t c_order = opts ? opts->row_order : VBCSR_ORDER_AUTO;
-  const bool plan_on_device = c_order == VBCSR_ORDER_AUTO || c_order == VBCSR_ORDER_ATOM;
-  std::vector<int64_t> prp, pobase;
-  std::vector<int32_t> poj;
-  if (eps > 0.0 || !plan_on_device) {
-    if ((rc = d2h(prp, so.crp, (size_t)n + 1, s)) || (rc = d2h(poj, so.oj, (size_t)nC, s)) ||
-        (rc = d2h(pobase, so.obase, (size_t)nC + 1, s)))
-      return rc;
-  }
   const int64_t *cls_begin = so.cls_begin;
   SpgemmParams sp{};
   sp.avals = static_cast<const double *>(A->dir[1].vals);
@@ -1156,7 +1144,6 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   double *cvals = nullptr, *cnorm = nullptr;
   if ((rc = tmp.alloc(&cvals, (size_t)nvals)) || (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
     return rc;
-  HIP_TRY(hipStreamSynchronize(s), "spgemm");
   st.ms_symbolic = ms_since(t0);
   sp.oi = so.oi;
   sp.oj = so.oj;
@@ -1192,102 +1179,54 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (e != hipSuccess) return hip_fail(e, "numeric stage");
   st.ms_numeric = ms;
 
-  // closing norm filter: drop computed blocks whose norm is below eps
+  // closing norm filter on the device: drop computed blocks whose norm is
+  // below eps (the pattern of C, its row pointer and values stay on the device)
   t0 = clk::now();
-  // C's structure: the symbolic pattern, or the filtered one built below
-  std::vector<int64_t> crp;
-  std::vector<int32_t> ccol;
-  const int64_t *c_rp = prp.data();
-  const int32_t *c_ci = poj.data();
-  int64_t c_nnzb = nC;
+  const int64_t *c_rp = so.crp;
+  const int32_t *c_ci = so.oj;
   const double *final_vals = cvals;
-  int64_t final_nvals = nvals;
+  int64_t c_nnzb = nC, final_nvals = nvals;
   if (eps > 0.0 && nC > 0) {
-    std::vector<double> nrm;
-    if ((rc = d2h(nrm, cnorm, (size_t)nC, s))) return rc;
-    HIP_TRY(hipStreamSynchronize(s), "spgemm");
-    // kept blocks and values per row, prefixes, then the rows in parallel
-    std::vector<int64_t> vrp((size_t)n + 1, 0);
-    crp.assign((size_t)n + 1, 0);
-    parallel_rows(n, [&](int32_t r0, int32_t r1) {
-      for (int32_t i = r0; i < r1; ++i) {
-        int64_t k = 0, v = 0;
-        for (int64_t c = prp[i]; c < prp[i + 1]; ++c)
-          if (!(nrm[c] < eps)) {
-            ++k;
-            v += pobase[c + 1] - pobase[c];
-          }
-        crp[i + 1] = k;
-        vrp[i + 1] = v;
-      }
-    });
-    for (int32_t i = 0; i < n; ++i) {
-      crp[i + 1] += crp[i];
-      vrp[i + 1] += vrp[i];
-    }
-    const int64_t nk = crp[n];
-    ccol.resize(nk);
-    RawVec<int64_t> sbase(nk), dbase(nk);
-    RawVec<int32_t> size(nk);
-    parallel_rows(n, [&](int32_t r0, int32_t r1) {
-      for (int32_t i = r0; i < r1; ++i) {
-        int64_t u = crp[i], pos = vrp[i];
-        for (int64_t c = prp[i]; c < prp[i + 1]; ++c) {
-          if (nrm[c] < eps) continue;
-          ccol[u] = poj[c];
-          sbase[u] = pobase[c];
-          dbase[u] = pos;
-          size[u] = (int32_t)(pobase[c + 1] - pobase[c]);
-          pos += size[u];
-          ++u;
-        }
-      }
-    });
-    const int64_t pos = vrp[n];
-    c_rp = crp.data();
-    c_ci = ccol.data();
-    c_nnzb = nk;
-    if (nk < nC) {
-      double *packed = nullptr;
-      int64_t *d_sb = nullptr, *d_db = nullptr;
-      int32_t *d_sz = nullptr;
-      if ((rc = tmp.up(&d_sb, sbase, s)) || (rc = tmp.up(&d_db, dbase, s)) ||
-          (rc = tmp.up(&d_sz, size, s)) || (rc = tmp.alloc(&packed, (size_t)pos)))
-        return rc;
-      e = launch_gather_blocks(cvals, d_sb, d_db, d_sz, (int64_t)size.size(), packed, s);
-      if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
-      final_vals = packed;
-      final_nvals = pos;
+    FilterOut fo;
+    e = spgemm_filter_device(n, nC, so.crp, so.oj, so.obase, cnorm, eps, cvals, fo, dalloc, s);
+    if (alloc_rc != VBCSR_OK) return alloc_rc;
+    if (e != hipSuccess) return hip_fail(e, "filter");
+    if (fo.nnzb < nC) {
+      c_rp = fo.rp;
+      c_ci = fo.ci;
+      final_vals = fo.vals;
+      c_nnzb = fo.nnzb;
+      final_nvals = fo.nvals;
     }
   }
   st.nnzb = c_nnzb;
   st.ms_filter = ms_since(t0);
 
-  // C as an ordinary handle over the same atoms
+  // C as an ordinary handle over the same atoms: laid out on the device in
+  // A's processing order (row order AUTO) or in atom order; an RCM or
+  // cluster order of C's own graph comes from the host planner, which takes
+  // the pattern back
   t0 = clk::now();
   vbcsr_plan_opts copts{};
   if (opts) copts = *opts;
-  if (plan_on_device) {
-    const int64_t *d_rp = so.crp;
-    const int32_t *d_ci = so.oj;
-    if (c_nnzb < nC) {   // the filtered pattern, from the host
-      int64_t *up_rp = nullptr;
-      int32_t *up_ci = nullptr;
-      if ((rc = tmp.up(&up_rp, crp, s)) || (rc = tmp.up(&up_ci, ccol, s))) return rc;
-      d_rp = up_rp;
-      d_ci = up_ci;
-    }
+  const int32_t c_order = copts.row_order;
+  if (c_order == VBCSR_ORDER_AUTO || c_order == VBCSR_ORDER_ATOM) {
     int32_t *d_ord = nullptr;
     if ((rc = tmp.alloc(&d_ord, (size_t)std::max<int32_t>(n, 1)))) return rc;
     e = c_order == VBCSR_ORDER_ATOM
             ? launch_iota(n, d_ord, s)
             : launch_order_from_rows(A->dir[0].rows, A->dir[0].npanels, A->off, n, d_ord, s);
     if (e != hipSuccess) return hip_fail(e, "order kernel launch");
-    rc = create_planned_on_device(out, A, c_nnzb, final_nvals, d_rp, d_ci, final_vals, d_ord,
+    rc = create_planned_on_device(out, A, c_nnzb, final_nvals, c_rp, c_ci, final_vals, d_ord,
                                   &copts, dalloc, s);
     if (alloc_rc != VBCSR_OK) return alloc_rc;
   } else {
-    rc = create_impl(out, n, b.data(), c_rp, c_nnzb ? c_ci : nullptr, final_vals, true,
+    std::vector<int64_t> hrp;
+    std::vector<int32_t> hci;
+    if ((rc = d2h(hrp, c_rp, (size_t)n + 1, s)) || (rc = d2h(hci, c_ci, (size_t)c_nnzb, s)))
+      return rc;
+    HIP_TRY(hipStreamSynchronize(s), "spgemm");
+    rc = create_impl(out, n, b.data(), hrp.data(), c_nnzb ? hci.data() : nullptr, final_vals, true,
                      final_nvals, VBCSR_FP64, &copts, stream);
   }
   if (rc) return rc;

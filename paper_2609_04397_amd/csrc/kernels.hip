@@ -1822,6 +1822,18 @@ __global__ void __launch_bounds__(kThreads) k_block_norms(const double *pages, c
   if (lane == 0) out[k] = sqrt(s);
 }
 
+// Zero the alignment gap after every panel and the slack after the last
+// (the values themselves are written by the packing): one thread per panel.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zero_gaps(const RowDesc *rows, int32_t np,
+                                                        int64_t n_values, T *vals) {
+  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (p >= np && !(p == 0 && np == 0)) return;
+  const int64_t s = np ? rows[p].vbase + (int64_t)rows[p].b * rows[p].K : 0;
+  const int64_t e = p + 1 < np ? rows[p + 1].vbase : n_values + kPageSlack;
+  for (int64_t x = s; x < e; ++x) vals[x] = T(0);
+}
+
 // dst[dbase[t] + e] = src[sbase[t] + e] for e < size[t]; one wave per block.
 __global__ void __launch_bounds__(kThreads) k_gather_blocks(const double *src,
                                                             const int64_t *sbase,
@@ -2036,6 +2048,18 @@ hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int
   const dim3 grid((unsigned)((nnzb + kWaves - 1) / kWaves));
   hipLaunchKernelGGL(k_block_norms, grid, dim3(kThreads), 0, s, pages, pos, blk_row, col_idx, b,
                      nnzb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_gaps(const RowDesc *rows, int32_t np, int64_t n_values, int elem_bytes,
+                            void *vals, hipStream_t s) {
+  const dim3 grid((unsigned)((std::max<int64_t>(np, 1) + kThreads - 1) / kThreads));
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_zero_gaps<double>, grid, dim3(kThreads), 0, s, rows, np, n_values,
+                       static_cast<double *>(vals));
+  else
+    hipLaunchKernelGGL(k_zero_gaps<float>, grid, dim3(kThreads), 0, s, rows, np, n_values,
+                       static_cast<float *>(vals));
   return hipGetLastError();
 }
 

@@ -205,10 +205,31 @@ hipError_t launch_order_from_rows(const RowDesc *rows, int32_t np, const int32_t
                                   int32_t *order, hipStream_t s);
 hipError_t launch_iota(int32_t n, int32_t *order, hipStream_t s);
 
+// Closing filter of the block product: block c of the pattern (row pointer
+// rp, n + 1 entries; columns ci; graph value offsets obase, nC + 1 entries;
+// values vals) is kept unless norm[c] < eps (a NaN norm keeps it); kept
+// blocks keep their order.  The filtered row pointer, columns and values are
+// carved out of one allocation made through `alloc` (left NULL when nothing
+// is removed: the inputs stand); their counts are returned on the host.
+struct FilterOut {
+  int64_t *rp = nullptr;
+  int32_t *ci = nullptr;
+  double *vals = nullptr;
+  int64_t nnzb = 0, nvals = 0;
+};
+hipError_t spgemm_filter_device(int32_t n, int64_t nC, const int64_t *rp, const int32_t *ci,
+                                const int64_t *obase, const double *norm, double eps,
+                                const double *vals, FilterOut &out, const DevAlloc &alloc,
+                                hipStream_t s);
 // out[k] = Frobenius norm of graph block k, read from forward pages at pos[k].
 hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int32_t *blk_row,
                               const int32_t *col_idx, const int32_t *b, int64_t nnzb, double *out,
                               hipStream_t s);
+// Zero the gaps of FP64 / FP32 pages (elem_bytes 8 or 4) that packing does
+// not write: after each of the np panels (rows in processing order) up to
+// the next panel, and kPageSlack values after the last.
+hipError_t launch_zero_gaps(const RowDesc *rows, int32_t np, int64_t n_values, int elem_bytes,
+                            void *vals, hipStream_t s);
 // dst[dbase[t] + e] = src[sbase[t] + e], e < size[t], t < nblk.
 hipError_t launch_gather_blocks(const double *src, const int64_t *sbase, const int64_t *dbase,
                                 const int32_t *size, int64_t nblk, double *dst, hipStream_t s);

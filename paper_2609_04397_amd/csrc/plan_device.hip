@@ -171,6 +171,42 @@ __global__ void __launch_bounds__(kT) k_pd_iota(int32_t n, int32_t *order) {
   if (p < n) order[p] = (int32_t)p;
 }
 
+// closing filter: keep flags and value counts of the symbolic pattern's
+// blocks (entry nC = 0)
+__global__ void __launch_bounds__(kT) k_flt_flags(int64_t nC, const double *norm, double eps,
+                                                  const int64_t *obase, int64_t *keep,
+                                                  int64_t *vsz) {
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c < nC) {
+    const bool kept = !(norm[c] < eps);
+    keep[c] = kept ? 1 : 0;
+    vsz[c] = kept ? obase[c + 1] - obase[c] : 0;
+  } else if (c == nC) {
+    keep[c] = 0;
+    vsz[c] = 0;
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_flt_compact(int64_t nC, const int64_t *keep,
+                                                    const int64_t *kidx, const int64_t *vpos,
+                                                    const int32_t *ci, const int64_t *obase,
+                                                    int32_t *ci_out, int64_t *sbase,
+                                                    int64_t *dbase, int32_t *size) {
+  const int64_t c = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (c >= nC || !keep[c]) return;
+  const int64_t t = kidx[c];
+  ci_out[t] = ci[c];
+  sbase[t] = obase[c];
+  dbase[t] = vpos[c];
+  size[t] = (int32_t)(obase[c + 1] - obase[c]);
+}
+
+__global__ void __launch_bounds__(kT) k_flt_rowptr(int32_t n, const int64_t *rp, const int64_t *kidx,
+                                                   int64_t *rp_out) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i <= n) rp_out[i] = kidx[rp[i]];
+}
+
 }  // namespace
 
 #define PD_TRY(x)                           \
@@ -329,6 +365,79 @@ hipError_t plan_device(const DevPlanIn &in, DevPlanOut &out, const DevAlloc &all
   PD_TRY(hipMemcpyAsync(&out.nnz, out.gbase + nnzb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   PD_TRY(hipStreamSynchronize(s));
   for (unsigned int c : hh) out.n_shapes += c ? 1 : 0;
+  return hipSuccess;
+}
+
+hipError_t spgemm_filter_device(int32_t n, int64_t nC, const int64_t *rp, const int32_t *ci,
+                                const int64_t *obase, const double *norm, double eps,
+                                const double *vals, FilterOut &out, const DevAlloc &alloc,
+                                hipStream_t s) {
+  out = FilterOut{};
+  PD_TRY(hipGetLastError());
+  auto sz = [](size_t elem, size_t count) { return (elem * (count ? count : 1) + 255) / 256 * 256; };
+  const size_t C1 = (size_t)nC + 1;
+  char *base = nullptr;
+  {
+    void *q = nullptr;
+    PD_TRY(alloc(&q, 4 * sz(8, C1)));
+    base = static_cast<char *>(q);
+  }
+  int64_t *keep = reinterpret_cast<int64_t *>(base);
+  int64_t *vsz = reinterpret_cast<int64_t *>(base + sz(8, C1));
+  int64_t *kidx = reinterpret_cast<int64_t *>(base + 2 * sz(8, C1));
+  int64_t *vpos = reinterpret_cast<int64_t *>(base + 3 * sz(8, C1));
+  void *cub_tmp = nullptr;
+  size_t cub_bytes = 0;
+  auto cub_run = [&](auto &&call) -> hipError_t {
+    size_t need = 0;
+    PD_TRY(call(nullptr, need));
+    if (need > cub_bytes) {
+      PD_TRY(alloc(&cub_tmp, need));
+      cub_bytes = need;
+    }
+    return call(cub_tmp, need);
+  };
+  hipLaunchKernelGGL(k_flt_flags, grid_for(nC + 1), dim3(kT), 0, s, nC, norm, eps, obase, keep, vsz);
+  PD_TRY(hipGetLastError());
+  PD_TRY(cub_run([&](void *t, size_t &bytes) {
+    return hipcub::DeviceScan::ExclusiveSum(t, bytes, keep, kidx, (int)C1, s);
+  }));
+  PD_TRY(cub_run([&](void *t, size_t &bytes) {
+    return hipcub::DeviceScan::ExclusiveSum(t, bytes, vsz, vpos, (int)C1, s);
+  }));
+  int64_t counts[2];
+  PD_TRY(hipMemcpyAsync(&counts[0], kidx + nC, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PD_TRY(hipMemcpyAsync(&counts[1], vpos + nC, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  PD_TRY(hipStreamSynchronize(s));
+  out.nnzb = counts[0];
+  out.nvals = counts[1];
+  if (out.nnzb == nC) return hipSuccess;   // nothing removed: the inputs stand
+  const size_t K = (size_t)out.nnzb;
+  {
+    void *q = nullptr;
+    PD_TRY(alloc(&q, sz(8, (size_t)n + 1) + sz(4, K) + 2 * sz(8, K) + sz(4, K) +
+                         sz(8, (size_t)out.nvals)));
+    char *p = static_cast<char *>(q);
+    out.rp = reinterpret_cast<int64_t *>(p);
+    p += sz(8, (size_t)n + 1);
+    out.ci = reinterpret_cast<int32_t *>(p);
+    p += sz(4, K);
+    int64_t *sbase = reinterpret_cast<int64_t *>(p);
+    p += sz(8, K);
+    int64_t *dbase = reinterpret_cast<int64_t *>(p);
+    p += sz(8, K);
+    int32_t *size = reinterpret_cast<int32_t *>(p);
+    p += sz(4, K);
+    out.vals = reinterpret_cast<double *>(p);
+    if (nC > 0) {
+      hipLaunchKernelGGL(k_flt_compact, grid_for(nC), dim3(kT), 0, s, nC, keep, kidx, vpos, ci,
+                         obase, out.ci, sbase, dbase, size);
+      PD_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_flt_rowptr, grid_for((int64_t)n + 1), dim3(kT), 0, s, n, rp, kidx, out.rp);
+    PD_TRY(hipGetLastError());
+    PD_TRY(launch_gather_blocks(vals, sbase, dbase, size, out.nnzb, out.vals, s));
+  }
   return hipSuccess;
 }
 
