@@ -1119,7 +1119,9 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
         p = loc - q * b1;
         if (p >= b1) { ++q; p -= b1; }
       }
-      const double v = load(g0 + rt.start + (int64_t)p * b2 + q);
+      // row-major sweep: the source is read in its own order (the load does
+      // not wait on the block lookup)
+      const double v = load(g0 + (sweep == 0 ? (int64_t)e : (int64_t)rt.start + (int64_t)p * b2 + q));
       if (KIND != 2) {
         // transposed panel of atom j: height b_j, row q, column k0 + p
         pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v);
