@@ -22,8 +22,9 @@ Timed alongside, each in a loop of its own with the same protocol:
   precision  the same operator in FP32 and BF16x3 at nrhs 64 (forward);
   fwd_bwd    the differentiation form on the 100,000-atom three-species
              operator (b = 1/4/9, nrhs 32): forward + adjoint + block-sampled
-             product as three raw calls and through the autograd function,
-             FP32 and plain FP64, and their ratio;
+             product as three raw calls and through the autograd function
+             (values in graph order, and in the forward-page layout), FP32
+             and plain FP64, and their ratio;
   c2_step    the 32^3 simple-cubic lattice (b = 13): SpMV, SpMM/SpMM^T/SDDMM
              at nrhs 32 and one Chebyshev step in FP64, FP32 and BF16x3 at
              nrhs 64 on the scaled operator.
@@ -330,7 +331,7 @@ def run_fwd_bwd(args, checks, only):
     block-sampled product at nrhs 32, as three raw calls and through the
     autograd function (loss sum(Y o G), so dY = G), FP32 against plain FP64."""
     import torch
-    from paper_2609_04397_amd import Matrix, spmm
+    from paper_2609_04397_amd import Matrix, spmm, spmm_pages
     from workloads import make_config
     op, vec = make_config("C5")
     dev = torch.device("cuda", 0)
@@ -349,23 +350,37 @@ def run_fwd_bwd(args, checks, only):
         def autograd_step(V=V, X=X, G=G, M=M):
             Y = spmm(V, X, M)
             return torch.autograd.grad(Y, (V, X), G)
-        rows.append(Row("c5_autograd_fwd_bwd_%s" % prec, autograd_step,
-                        sum(r.nbytes for r in rows), sum(r.flops for r in rows), 32, prec))
+        raw_bytes, raw_flops = sum(r.nbytes for r in rows), sum(r.flops for r in rows)
+        rows.append(Row("c5_autograd_fwd_bwd_%s" % prec, autograd_step, raw_bytes, raw_flops, 32,
+                        prec))
+        # the same step with the parameter in the forward-page layout: no
+        # packing in the forward, the transposed pages rebuilt for dX
+        Mp = Matrix.from_operator(op, prec=prec)
+        Pg = Mp.get_pages().requires_grad_(True)
+
+        def pages_step(P=Pg, X=X, G=G, M=Mp):
+            Y = spmm_pages(P, X, M)
+            return torch.autograd.grad(Y, (P, X), G)
+        rows.append(Row("c5_autograd_pages_fwd_bwd_%s" % prec, pages_step, raw_bytes, raw_flops,
+                        32, prec))
         res, _ = time_rows(rows, args.steps, args.warmup, only)
         for r in rows:
             if r.capture is not None and (not only or r.name in only):
                 checks.append((r.name, r.capture()))
         out["rows"] += res
         raw = [r for r in res if not r["kernel"].startswith("c5_autograd")]
-        ag = [r for r in res if r["kernel"].startswith("c5_autograd")]
         if len(raw) == 3:
             out["%s_ms" % prec] = round(sum(r["avg_ms"] for r in raw), 4)
-        if ag:
-            out["autograd_%s_ms" % prec] = ag[0]["avg_ms"]
-            if len(raw) == 3:
-                out["autograd_over_raw_%s" % prec] = round(ag[0]["avg_ms"] / out["%s_ms" % prec], 3)
+        for key, name in (("autograd", "c5_autograd_fwd_bwd_"),
+                          ("autograd_pages", "c5_autograd_pages_fwd_bwd_")):
+            ag = [r for r in res if r["kernel"] == name + prec]
+            if ag:
+                out["%s_%s_ms" % (key, prec)] = ag[0]["avg_ms"]
+                if len(raw) == 3:
+                    out["%s_over_raw_%s" % (key, prec)] = round(ag[0]["avg_ms"] / out["%s_ms" % prec], 3)
         M.close()
-        del V, X, G
+        Mp.close()
+        del V, X, G, Pg
     if "fp32_ms" in out and "fp64_ms" in out:
         out["ratio_fp32_over_fp64"] = round(out["fp32_ms"] / out["fp64_ms"], 4)
     return out

@@ -28,7 +28,8 @@
  * Streams: `stream` is a hipStream_t (NULL = the default stream).  Products
  * are enqueued asynchronously; the library synchronises the device only in
  * vbcsr_create, vbcsr_set_values (host input), vbcsr_cheb_moments(_doubled),
- * vbcsr_spgemm, vbcsr_get_structure and vbcsr_destroy.  A handle is immutable except through vbcsr_set_values;
+ * vbcsr_spgemm, vbcsr_get_structure and vbcsr_destroy.  A handle is immutable except through
+ * vbcsr_set_values, vbcsr_use_pages and vbcsr_refresh_transposed;
  * products on different streams may run concurrently on one handle, but
  * must not overlap a vbcsr_set_values on it.
  */
@@ -210,6 +211,48 @@ int vbcsr_spmm_t(const vbcsr_mat *A, const void *X, int64_t ldx, void *Y, int64_
  */
 int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X, int64_t ldx,
                 int32_t nrhs, void *dA, void *stream);
+
+/*
+ * Page-layout values (FP64 and FP32 handles).  No passage of the paper
+ * defines these calls: they let a caller that differentiates with respect
+ * to the block values (vbcsr_sddmm) keep that parameter in the operator's
+ * own forward-page layout, so a training step repacks nothing for the
+ * forward product and rebuilds only the transposed pages for the adjoint.  A page buffer holds
+ * vbcsr_page_size() entries of the handle's value type: every block value at
+ * its forward-page position, zeros in the alignment gaps between panels and
+ * in the slack after the last (the products read those as zeros).
+ *
+ * vbcsr_page_size -- entries of a page buffer.
+ * vbcsr_get_pages -- copy the current forward values, page layout, into the
+ *   device buffer `pages` (on `stream`).
+ * vbcsr_use_pages -- from now on the forward products (vbcsr_spmm, the
+ *   Chebyshev helpers, vbcsr_get_values, the block product's B) read the
+ *   forward values from the caller's device buffer `pages`, which is not
+ *   copied: it must stay allocated and keep the layout above while in use.
+ *   NULL returns to the handle's own pages (as the last vbcsr_create or
+ *   vbcsr_set_values left them).  Either way the transposed pages become
+ *   stale: vbcsr_spmm_t, and vbcsr_spgemm with this handle as A, return
+ *   EINVAL until vbcsr_refresh_transposed.  vbcsr_set_values returns to the
+ *   handle's own pages and rewrites both page sets.  Changes the handle: no
+ *   product may run on it meanwhile.  No device work.
+ * vbcsr_refresh_transposed -- rebuild the transposed pages from the current
+ *   forward values (a kernel on `stream`); call it again after changing the
+ *   contents of a buffer in use.  The first call on a handle also sorts its
+ *   blocks into transposed-page order (kept with the handle) and
+ *   synchronises `stream`.
+ * vbcsr_sddmm_pages -- vbcsr_sddmm with dA written in the page layout:
+ *   dA receives vbcsr_page_size() entries (values at their forward-page
+ *   positions, zeros in the gaps and the slack), the gradient of the page
+ *   buffer when the forward product reads its values from it.
+ * Errors: EINVAL (null arguments, bad vectors, overlap), EUNSUPPORTED
+ * (BF16X3 handles), EHIP.
+ */
+int vbcsr_page_size(const vbcsr_mat *A, int64_t *n_page_values);
+int vbcsr_get_pages(const vbcsr_mat *A, void *pages, void *stream);
+int vbcsr_use_pages(vbcsr_mat *A, const void *pages);
+int vbcsr_refresh_transposed(vbcsr_mat *A, void *stream);
+int vbcsr_sddmm_pages(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
+                      int64_t ldx, int32_t nrhs, void *dA, void *stream);
 
 /*
  * vbcsr_cheb_workspace_bytes -- device workspace, in bytes, that

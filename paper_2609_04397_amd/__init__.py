@@ -4,11 +4,11 @@
 the package itself touches neither.
 """
 
-__all__ = ["Matrix", "spmm", "Halo", "VbcsrError"]
+__all__ = ["Matrix", "spmm", "spmm_pages", "Halo", "VbcsrError"]
 
 
 def __getattr__(name):
-    if name in ("Matrix", "spmm"):
+    if name in ("Matrix", "spmm", "spmm_pages"):
         from . import matrix
         return getattr(matrix, name)
     if name == "Halo":

@@ -69,6 +69,11 @@ SIGNATURES = {
     "vbcsr_spmm": (_int, [_p, _p, _i64, _p, _i64, _i32, _f64, _f64, _p]),
     "vbcsr_spmm_t": (_int, [_p, _p, _i64, _p, _i64, _i32, _f64, _f64, _p]),
     "vbcsr_sddmm": (_int, [_p, _p, _i64, _p, _i64, _i32, _p, _p]),
+    "vbcsr_page_size": (_int, [_p, ctypes.POINTER(_i64)]),
+    "vbcsr_get_pages": (_int, [_p, _p, _p]),
+    "vbcsr_use_pages": (_int, [_p, _p]),
+    "vbcsr_refresh_transposed": (_int, [_p, _p]),
+    "vbcsr_sddmm_pages": (_int, [_p, _p, _i64, _p, _i64, _i32, _p, _p]),
     "vbcsr_cheb_workspace_bytes": (_int, [_p, _i32, _i32, ctypes.POINTER(_i64)]),
     "vbcsr_cheb_moments": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),
     "vbcsr_cheb_moments_doubled": (_int, [_p, _p, _i64, _i32, _i32, _p, _p, _i64, _p]),

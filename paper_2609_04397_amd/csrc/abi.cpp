@@ -122,6 +122,7 @@ struct DevDir {
   int64_t *blk_pos = nullptr;
   int32_t *blk_k0 = nullptr;
   int32_t *blk_prow = nullptr;
+  int32_t *blk_order = nullptr;  // graph blocks in page order (FP64/FP32 packing)
   int64_t *colg = nullptr;    // forward direction only
   int64_t n_values = 0, n_values16 = 0;
   int32_t npanels = 0;        // forward: block rows; transposed: block columns
@@ -152,6 +153,10 @@ struct vbcsr_mat {
   int32_t *blk_row = nullptr;
   int64_t *gbase = nullptr;
   DevDir dir[2];  // 0 = forward pages, 1 = transposed pages
+  // forward values read from a caller's page buffer (vbcsr_use_pages):
+  // own_fwd keeps the handle's own forward pages meanwhile
+  void *own_fwd = nullptr;
+  bool tr_stale = false;  // transposed pages not rebuilt since the forward source changed
   std::vector<void *> owned;
 };
 
@@ -265,6 +270,8 @@ Route route(const vbcsr_mat *A, int32_t nrhs) {
 int product(const vbcsr_mat *A, int d, const void *X, int64_t ldx, const void *Yin, int64_t ldyin,
             void *Yout, int64_t ldy, int32_t nrhs, double alpha, double beta, const void *R,
             int64_t ldr, double *mom, hipStream_t s) {
+  if (d == 1 && A->tr_stale)
+    return fail(VBCSR_EINVAL, "the transposed pages are stale: call vbcsr_refresh_transposed");
   const DevDir &D = A->dir[d];
   const Route rt = route(A, nrhs);
   hipError_t e;
@@ -662,6 +669,12 @@ int vbcsr_set_values(vbcsr_mat *A, const void *values, int on_device, int dtype,
   if (!values) return fail(VBCSR_EINVAL, "values is NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t es = dtype == 0 ? 8 : 4;
+  // back to the handle's own forward pages; both page sets are rewritten
+  if (A->own_fwd) {
+    A->dir[0].vals = A->own_fwd;
+    A->own_fwd = nullptr;
+  }
+  A->tr_stale = false;
   if (on_device) return pack_all(A, values, dtype, s);
   void *stage = nullptr;
   int rc = dev_alloc(&stage, es * A->nnz);
@@ -732,6 +745,127 @@ int vbcsr_sddmm(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
   return VBCSR_OK;
 } catch (...) {
   return api_exception("vbcsr_sddmm");
+}
+
+int vbcsr_page_size(const vbcsr_mat *A, int64_t *n_page_values) try {
+  if (!A || !n_page_values) return fail(VBCSR_EINVAL, "NULL argument");
+  if (A->prec == VBCSR_BF16X3)
+    return fail(VBCSR_EUNSUPPORTED, "BF16X3 handles keep hi/lo pages: no page-layout values");
+  *n_page_values = A->dir[0].n_values + kPageSlack;
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_page_size");
+}
+
+int vbcsr_get_pages(const vbcsr_mat *A, void *pages, void *stream) try {
+  int64_t n = 0;
+  if (int rc = vbcsr_page_size(A, &n)) return rc;
+  if (!pages) return fail(VBCSR_EINVAL, "pages is NULL");
+  HIP_TRY(hipMemcpyAsync(pages, A->dir[0].vals, vec_elem(A) * (size_t)n, hipMemcpyDeviceToDevice,
+                         static_cast<hipStream_t>(stream)),
+          "hipMemcpyAsync");
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_get_pages");
+}
+
+int vbcsr_use_pages(vbcsr_mat *A, const void *pages) try {
+  int64_t n = 0;
+  if (int rc = vbcsr_page_size(A, &n)) return rc;
+  if (pages) {
+    if (!A->own_fwd) A->own_fwd = A->dir[0].vals;
+    A->dir[0].vals = const_cast<void *>(pages);
+  } else if (A->own_fwd) {
+    A->dir[0].vals = A->own_fwd;
+    A->own_fwd = nullptr;
+  }
+  A->tr_stale = true;
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_use_pages");
+}
+
+int vbcsr_refresh_transposed(vbcsr_mat *A, void *stream) try {
+  int64_t n = 0;
+  if (int rc = vbcsr_page_size(A, &n)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  DevDir &D = A->dir[1];
+  if (A->nnz > 0 && !D.blk_order) {
+    // first call: the blocks in transposed-page order (the rebuild walks the
+    // pages it writes)
+    int rc;
+    if ((rc = alloc_into(A, &D.blk_order, (size_t)A->nnzb))) return rc;
+    std::vector<void *> tmp;
+    const DevAlloc alloc = [&](void **q, size_t bytes) -> hipError_t {
+      if (dev_alloc(q, bytes) != VBCSR_OK) return hipErrorOutOfMemory;
+      tmp.push_back(*q);
+      return hipSuccess;
+    };
+    hipError_t e = launch_page_order(D.blk_pos, A->nnzb, D.n_values, D.blk_order, alloc, s);
+    if (e == hipSuccess && !tmp.empty()) e = hipStreamSynchronize(s);
+    for (void *q : tmp) (void)hipFree(q);
+    if (e != hipSuccess) {
+      D.blk_order = nullptr;   // still owned by the handle, freed with it
+      return hip_fail(e, "page order");
+    }
+  }
+  if (A->nnz > 0) {
+    PackParams pp{};
+    pp.b = A->b;
+    pp.blk_row = A->blk_row;
+    pp.col_idx = A->col_idx;
+    pp.gbase = A->gbase;
+    pp.nnzb = A->nnzb;
+    pp.dst_kind = A->prec == VBCSR_FP64 ? 0 : 1;
+    for (int d = 0; d < 2; ++d) {
+      pp.dir[d].pos = A->dir[d].blk_pos;
+      pp.dir[d].k0 = A->dir[d].blk_k0;
+      pp.dir[d].prow = A->dir[d].blk_prow;
+    }
+    pp.dir[1].dst = A->dir[1].vals;
+    hipError_t e = launch_pack_dst(pp, D.blk_order, 1, A->dir[0].vals, 2, s);
+    if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
+  }
+  A->tr_stale = false;
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_refresh_transposed");
+}
+
+int vbcsr_sddmm_pages(const vbcsr_mat *A, const void *dY, int64_t lddy, const void *X,
+                      int64_t ldx, int32_t nrhs, void *dA, void *stream) try {
+  int64_t n = 0;
+  if (int rc = vbcsr_page_size(A, &n)) return rc;
+  if (int rc = check_vectors(A, dY, A->N_rows, lddy, X, A->N, ldx, nrhs, false)) return rc;
+  if (!dA) return fail(VBCSR_EINVAL, "dA is NULL");
+  const size_t e = vec_elem(A);
+  const size_t abytes = e * (size_t)n;
+  if (ranges_overlap(dA, abytes, dY, span_bytes(A->N_rows, lddy, nrhs, e)) ||
+      ranges_overlap(dA, abytes, X, span_bytes(A->N, ldx, nrhs, e)))
+    return fail(VBCSR_EINVAL, "dA overlaps an input");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevDir &D = A->dir[0];
+  hipError_t err = hipSuccess;
+  if (A->nnz > 0) {
+    if (A->prec == VBCSR_FP64) {
+      SddmmParams<double> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const double *>(dY),
+                            lddy, static_cast<const double *>(X), ldx, nrhs,
+                            static_cast<double *>(dA), A->N, 1};
+      err = launch_sddmm_f64(p, s);
+    } else {
+      SddmmParams<float> p{D.rows, D.npanels, D.colx, D.colg, static_cast<const float *>(dY),
+                           lddy, static_cast<const float *>(X), ldx, nrhs,
+                           static_cast<float *>(dA), A->N, 1};
+      err = launch_sddmm_f32(p, s);
+    }
+    if (err != hipSuccess) return hip_fail(err, "sddmm kernel launch");
+  }
+  // the gaps between panels and the slack read as zero
+  err = launch_zero_gaps(D.rows, D.npanels, D.n_values, (int)e, dA, s);
+  if (err != hipSuccess) return hip_fail(err, "gap kernel launch");
+  return VBCSR_OK;
+} catch (...) {
+  return api_exception("vbcsr_sddmm_pages");
 }
 
 int vbcsr_cheb_workspace_bytes(const vbcsr_mat *A, int32_t nrhs, int32_t degree, int64_t *bytes) try {
@@ -1070,6 +1204,8 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   if (int rc2 = require_square(A, "vbcsr_spgemm")) return rc2;
   if (int rc2 = require_square(B, "vbcsr_spgemm")) return rc2;
   if (A->n != B->n) return fail(VBCSR_EINVAL, "A and B must be over the same atoms");
+  if (A->tr_stale)
+    return fail(VBCSR_EINVAL, "A's transposed pages are stale: call vbcsr_refresh_transposed");
   if (opts && (opts->rows_per_wg != 0 || opts->path < 0 || opts->path > VBCSR_PATH_MFMA ||
                opts->row_order < VBCSR_ORDER_AUTO || opts->row_order > VBCSR_ORDER_CLUSTER))
     return fail(VBCSR_EINVAL, "invalid plan options");

@@ -1027,6 +1027,14 @@ __global__ void __launch_bounds__(kThreads) k_spmm_bf16x3_vx(FwdParams<float> P)
 // block width, corrected by one step (exact for offsets below 2^12 and
 // widths up to 64).
 constexpr int kPackRun = 8;
+constexpr int kPackChunk = 4;
+
+// Output map of panel column kk for the block-sampled product written in the
+// forward pages' layout: column kk of the panel starts at vbase + kk * b and
+// its rows are consecutive (stride 1).
+__device__ __forceinline__ int64_t page_map(const RowDesc &rd, int kk) {
+  return ((rd.vbase + (int64_t)kk * rd.b) << 7) | 1;
+}
 
 __device__ __forceinline__ void pack_store(const PackDir &D, int kind, int64_t pos, int k0,
                                            int64_t vb16, int h, int r, int c, double v) {
@@ -1056,7 +1064,10 @@ struct PackRec {       // one block of a run, in LDS
 };
 static_assert(sizeof(PackRec) == 64, "PackRec layout");
 
-template <int SRC, int KIND>  // SRC 0/1: double/float source; KIND: dst_kind
+// SRC 0/1: double / float source in graph order, both page sets written;
+// SRC 2: the forward pages (of the page type) as source, only the transposed
+// pages written.  KIND: dst_kind.
+template <int SRC, int KIND>
 __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src) {
   __shared__ PackRec tab_all[kWaves * kPackRun];
   const int64_t k0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
@@ -1095,43 +1106,159 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
   const int len = __builtin_amdgcn_readlane(start + n, nb - 1);
 #pragma unroll
   for (int u = 0; u < kPackRun; ++u) st[u] = u < nb ? __builtin_amdgcn_readlane(start, u) : len;
+  // SRC 2: the source is the forward pages, of the destination type
   auto load = [&](int64_t at) {
-    return SRC == 0 ? static_cast<const double *>(src)[at]
-                    : (double)static_cast<const float *>(src)[at];
+    if constexpr (SRC == 0 || (SRC == 2 && KIND == 0))
+      return static_cast<const double *>(src)[at];
+    else
+      return (double)static_cast<const float *>(src)[at];
   };
-  // sweep 0 in row-major order, sweep 1 (BF16 only) in column-major order
+  // sweep 0 in row-major order, sweep 1 (BF16 only) in column-major order.
+  // Elements go in chunks of kPackChunk per lane: every load of a chunk is
+  // issued before its first store, so a lane waits once per chunk (a lane
+  // has only a few elements when blocks are small).
   for (int sweep = 0; sweep < (KIND == 2 ? 2 : 1); ++sweep) {
-#pragma unroll 4
-    for (int e = lane; e < len; e += 64) {
-      int t = 0;
+    for (int e0 = lane; e0 < len; e0 += 64 * kPackChunk) {
+      double v[kPackChunk];
+      int tt[kPackChunk], pp[kPackChunk], qq[kPackChunk];
 #pragma unroll
-      for (int u = 1; u < kPackRun; ++u) t += e >= st[u] ? 1 : 0;
-      const PackRec &rt = tab[t];
-      const int b1 = rt.bi, b2 = rt.bj;
-      const int loc = e - rt.start;
+      for (int c = 0; c < kPackChunk; ++c) {
+        const int e = e0 + 64 * c;
+        const int ec = e < len ? e : len - 1;
+        int t = 0;
+#pragma unroll
+        for (int u = 1; u < kPackRun; ++u) t += ec >= st[u] ? 1 : 0;
+        const PackRec &rt = tab[t];
+        const int b1 = rt.bi, b2 = rt.bj;
+        const int loc = ec - rt.start;
+        int p, q;
+        if (sweep == 0) {   // row-major: p = loc / b2
+          p = (int)((float)loc * __builtin_amdgcn_rcpf((float)b2));
+          q = loc - p * b2;
+          if (q >= b2) { ++p; q -= b2; }
+        } else {            // column-major: q = loc / b1
+          q = (int)((float)loc * __builtin_amdgcn_rcpf((float)b1));
+          p = loc - q * b1;
+          if (p >= b1) { ++q; p -= b1; }
+        }
+        tt[c] = t;
+        pp[c] = p;
+        qq[c] = q;
+        // row-major sweep: the source is read in its own order (the load
+        // does not wait on the block lookup)
+        v[c] = SRC == 2 ? load(rt.pf + (int64_t)q * b1 + p)
+                        : load(g0 + (sweep == 0 ? (int64_t)ec
+                                                : (int64_t)rt.start + (int64_t)p * b2 + q));
+      }
+#pragma unroll
+      for (int c = 0; c < kPackChunk; ++c) {
+        if (e0 + 64 * c >= len) break;
+        const PackRec &rt = tab[tt[c]];
+        const int b1 = rt.bi, b2 = rt.bj, p = pp[c], q = qq[c];
+        if (SRC == 2) {
+          pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v[c]);
+        } else if (KIND != 2) {
+          // transposed panel of atom j: height b_j, row q, column k0 + p
+          pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v[c]);
+          // forward panel of atom i: height b_i, row p, column k0 + q
+          pack_store(P.dir[0], KIND, rt.pf, 0, 0, b1, p, q, v[c]);
+        } else if (sweep == 0) {
+          pack_store(P.dir[0], KIND, rt.pf, rt.kf, rt.vf, b1, p, q, v[c]);
+        } else {
+          pack_store(P.dir[1], KIND, rt.pt, rt.kt, rt.vt, b2, q, p, v[c]);
+        }
+      }
+    }
+  }
+}
+
+// Value packing in the order of the pages written: one wave per run of
+// kPackRun consecutive blocks of direction DIR's page order (`order`), whose
+// destination values are contiguous apart from the alignment gap between two
+// panels, so stores form whole contiguous runs whatever the block sizes (in
+// source order, neighbouring small blocks land in different panels and their
+// lines are written in pieces by different waves).  Lane l takes elements
+// l, l + 64, ... of the run in destination order; sources: SRC 0 / 1 graph
+// order (double / float, row-major blocks), SRC 2 the forward pages
+// (column-major blocks, of the page type).  DIR 0 writes the forward pages
+// (column-major blocks), DIR 1 the transposed pages (row-major blocks).
+template <int SRC, int KIND, int DIR>   // KIND 0 / 1: double / float pages
+__global__ void __launch_bounds__(kThreads) k_pack_dst(PackParams P, const int32_t *order,
+                                                       const void *src) {
+  using T = typename std::conditional<KIND == 0, double, float>::type;
+  __shared__ int32_t tab_b[kWaves * kPackRun * 2];
+  __shared__ int64_t tab_p[kWaves * kPackRun * 2];
+  const int64_t u0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
+  if (u0 >= P.nnzb) return;
+  const int lane = threadIdx.x & 63;
+  const int nb = (int)min((int64_t)kPackRun, P.nnzb - u0);
+  int32_t *tb = tab_b + wave_id() * kPackRun * 2;
+  int64_t *tp = tab_p + wave_id() * kPackRun * 2;
+  int n = 0;
+  if (lane < nb) {
+    const int32_t k = order[u0 + lane];
+    const int bi = P.b[P.blk_row[k]], bj = P.b[P.col_idx[k]];
+    n = bi * bj;
+    tb[2 * lane] = bi;
+    tb[2 * lane + 1] = bj;
+    tp[2 * lane] = SRC == 2 ? P.dir[0].pos[k] : P.gbase[k];
+    tp[2 * lane + 1] = P.dir[DIR].pos[k];
+  }
+  // run-relative first value of each block: exclusive prefix sum of n
+  int incl = n;
+#pragma unroll
+  for (int o = 1; o < kPackRun; o <<= 1) {
+    const int t = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += t;
+  }
+  const int start = incl - n;
+  wave_lds_sync();
+  int st[kPackRun];
+  const int len = __builtin_amdgcn_readlane(incl, nb - 1);
+#pragma unroll
+  for (int u = 0; u < kPackRun; ++u) st[u] = u < nb ? __builtin_amdgcn_readlane(start, u) : len;
+  T *dst = static_cast<T *>(P.dir[DIR].dst);
+  // chunks of kPackChunk elements per lane: all loads before the stores
+  for (int e0 = lane; e0 < len; e0 += 64 * kPackChunk) {
+    T v[kPackChunk];
+    int64_t d[kPackChunk];
+#pragma unroll
+    for (int c = 0; c < kPackChunk; ++c) {
+      const int e = min(e0 + 64 * c, len - 1);
+      // the block of element e (starts ascending, st[0] = 0) and its first value
+      int t = 0, stt = 0;
+#pragma unroll
+      for (int u = 1; u < kPackRun; ++u)
+        if (e >= st[u]) {
+          t = u;
+          stt = st[u];
+        }
+      const int b1 = tb[2 * t], b2 = tb[2 * t + 1];
+      const int l = e - stt;
+      // destination element (p, q) of the b1 x b2 block
       int p, q;
-      if (sweep == 0) {   // row-major: p = loc / b2
-        p = (int)((float)loc * __builtin_amdgcn_rcpf((float)b2));
-        q = loc - p * b2;
+      if (DIR == 1) {   // row-major: p = l / b2
+        p = (int)((float)l * __builtin_amdgcn_rcpf((float)b2));
+        q = l - p * b2;
         if (q >= b2) { ++p; q -= b2; }
-      } else {            // column-major: q = loc / b1
-        q = (int)((float)loc * __builtin_amdgcn_rcpf((float)b1));
-        p = loc - q * b1;
+      } else {          // column-major: q = l / b1
+        q = (int)((float)l * __builtin_amdgcn_rcpf((float)b1));
+        p = l - q * b1;
         if (p >= b1) { ++q; p -= b1; }
       }
-      // row-major sweep: the source is read in its own order (the load does
-      // not wait on the block lookup)
-      const double v = load(g0 + (sweep == 0 ? (int64_t)e : (int64_t)rt.start + (int64_t)p * b2 + q));
-      if (KIND != 2) {
-        // transposed panel of atom j: height b_j, row q, column k0 + p
-        pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v);
-        // forward panel of atom i: height b_i, row p, column k0 + q
-        pack_store(P.dir[0], KIND, rt.pf, 0, 0, b1, p, q, v);
-      } else if (sweep == 0) {
-        pack_store(P.dir[0], KIND, rt.pf, rt.kf, rt.vf, b1, p, q, v);
-      } else {
-        pack_store(P.dir[1], KIND, rt.pt, rt.kt, rt.vt, b2, q, p, v);
-      }
+      const int64_t so = tp[2 * t] + (SRC == 2 ? (int64_t)q * b1 + p : (int64_t)p * b2 + q);
+      if constexpr (SRC == 0)
+        v[c] = (T) static_cast<const double *>(src)[so];
+      else if constexpr (SRC == 1)
+        v[c] = (T) static_cast<const float *>(src)[so];
+      else
+        v[c] = static_cast<const T *>(src)[so];
+      d[c] = tp[2 * t + 1] + l;
+    }
+#pragma unroll
+    for (int c = 0; c < kPackChunk; ++c) {
+      if (e0 + 64 * c >= len) break;
+      dst[d[c]] = v[c];
     }
   }
 }
@@ -1203,7 +1330,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_mfma(SddmmParams<T> P) {
       tl.kin = kc < K;
       const int kk = tl.kin ? kc : K - 1;
       tl.xrow = P.X + (int64_t)cx[kk] * P.ldx;
-      tl.g = cg[kk];
+      tl.g = P.page_out ? page_map(rd, kk) : cg[kk];
 #pragma unroll
       for (int ch = 0; ch < NCH; ++ch) ldrun(tl.xrow, ch, tl.kin && ch < nch, tl.bv[ch]);
     };
@@ -1310,7 +1437,7 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_lds(SddmmParams<T> P) {
       const int kc = j * 16 + m;
       const int kk = kc < K ? kc : K - 1;
       const int32_t xr = cx[kk];
-      const int64_t g = cg[kk];
+      const int64_t g = P.page_out ? page_map(rd, kk) : cg[kk];
       V acc0 = V{}, acc1 = V{};
       for (int pass = 0; pass < npass; ++pass) {
         const int c0 = pass * CW;
@@ -1414,7 +1541,10 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
     return __builtin_bit_cast(v4u32, __builtin_amdgcn_raw_buffer_load_b128(
                                          rc, (uint32_t)(j * 16 + 4 * kq) * 4u, 0, 0));
   };
-  auto gmap_of = [&](int j) { return cg[min(j * 16 + m, K - 1)]; };
+  auto gmap_of = [&](int j) {
+    const int kk = min(j * 16 + m, K - 1);
+    return P.page_out ? page_map(rd, kk) : cg[kk];
+  };
   const int sslot = lane & 15;
   auto issue = [&](int s, v4u32 xr) {
     const int j = s / NCH, ch = s % NCH;
@@ -1953,7 +2083,10 @@ hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipS
     case 2: hipLaunchKernelGGL((k_pack<0, 2>), grid, dim3(kThreads), 0, s, p, src); break;
     case 3: hipLaunchKernelGGL((k_pack<1, 0>), grid, dim3(kThreads), 0, s, p, src); break;
     case 4: hipLaunchKernelGGL((k_pack<1, 1>), grid, dim3(kThreads), 0, s, p, src); break;
-    default: hipLaunchKernelGGL((k_pack<1, 2>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 5: hipLaunchKernelGGL((k_pack<1, 2>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 6: hipLaunchKernelGGL((k_pack<2, 0>), grid, dim3(kThreads), 0, s, p, src); break;
+    case 7: hipLaunchKernelGGL((k_pack<2, 1>), grid, dim3(kThreads), 0, s, p, src); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -2050,6 +2183,28 @@ hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int
   const dim3 grid((unsigned)((nnzb + kWaves - 1) / kWaves));
   hipLaunchKernelGGL(k_block_norms, grid, dim3(kThreads), 0, s, pages, pos, blk_row, col_idx, b,
                      nnzb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_dst(const PackParams &p, const int32_t *order, int dir, const void *src,
+                           int src_dtype, hipStream_t s) {
+  if (p.nnzb == 0) return hipSuccess;
+  const int64_t waves = (p.nnzb + kPackRun - 1) / kPackRun;
+  const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves));
+  const int sel = (src_dtype * 2 + p.dst_kind) * 2 + dir;
+  switch (sel) {
+    case 0: hipLaunchKernelGGL((k_pack_dst<0, 0, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 1: hipLaunchKernelGGL((k_pack_dst<0, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 2: hipLaunchKernelGGL((k_pack_dst<0, 1, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 3: hipLaunchKernelGGL((k_pack_dst<0, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 4: hipLaunchKernelGGL((k_pack_dst<1, 0, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 5: hipLaunchKernelGGL((k_pack_dst<1, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 6: hipLaunchKernelGGL((k_pack_dst<1, 1, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 7: hipLaunchKernelGGL((k_pack_dst<1, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 9: hipLaunchKernelGGL((k_pack_dst<2, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    case 11: hipLaunchKernelGGL((k_pack_dst<2, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

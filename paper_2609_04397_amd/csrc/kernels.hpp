@@ -10,6 +10,9 @@
 
 namespace vbcsr {
 
+// device allocation callback: the caller owns (and later frees) what it returns
+using DevAlloc = std::function<hipError_t(void **, size_t)>;
+
 // Arguments of one product launch over all panels of one direction.
 //   Yout[r, c] = alpha * (A X)[r, c] + beta * Yin[r, c]   (Yin unread if beta == 0)
 // With `mom` set, the kernel also adds R[r, c] * Yout[r, c] (in FP64) of its
@@ -66,7 +69,19 @@ struct PackParams {
   int dst_kind;             // 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages
   PackDir dir[2];           // 0: forward panels (column-major blocks), 1: transposed
 };
+// src_dtype 0 / 1: graph-order double / float source, both page sets written;
+// 2: the forward pages (dst_kind 0 or 1) as source, only the transposed pages
+// (dir[1]) written.
 hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipStream_t s);
+// One page set (dir 0 forward, 1 transposed; dst_kind 0 or 1) written in its
+// own order: order[u] = graph block at page-order position u of direction
+// dir.  src_dtype as launch_pack (2 only with dir 1).
+hipError_t launch_pack_dst(const PackParams &p, const int32_t *order, int dir, const void *src,
+                           int src_dtype, hipStream_t s);
+// order[u] = graph block whose position pos[block] is the u-th smallest
+// (page order of one direction; positions are distinct, below n_values).
+hipError_t launch_page_order(const int64_t *pos, int64_t nnzb, int64_t n_values, int32_t *order,
+                             const DevAlloc &alloc, hipStream_t s);
 
 // dA (graph order) = block-sampled dY X^T, over the forward panels.
 template <typename T>
@@ -82,6 +97,7 @@ struct SddmmParams {
   int32_t nrhs;
   T *dA;
   int64_t xrows;         // rows of X (columns of the operator)
+  int32_t page_out;      // 1: dA in the forward pages' layout (colg unused)
 };
 hipError_t launch_sddmm_f64(const SddmmParams<double> &p, hipStream_t s);
 hipError_t launch_sddmm_f32(const SddmmParams<float> &p, hipStream_t s);
@@ -142,7 +158,6 @@ hipError_t launch_spgemm_numeric(const SpgemmParams &p, int cls, int max_b, hipS
 // products pa (apos << 8 | b_k) / pb (bpos) in A's stored order of k, and
 // the blocks grouped by tile class (order, stable; class k holds
 // order[cls_begin[k] .. cls_begin[k+1])).
-using DevAlloc = std::function<hipError_t(void **, size_t)>;
 struct SymbolicIn {
   int32_t n;
   int64_t annzb;

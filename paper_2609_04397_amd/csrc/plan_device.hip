@@ -441,4 +441,26 @@ hipError_t spgemm_filter_device(int32_t n, int64_t nC, const int64_t *rp, const 
   return hipSuccess;
 }
 
+hipError_t launch_page_order(const int64_t *pos, int64_t nnzb, int64_t n_values, int32_t *order,
+                             const DevAlloc &alloc, hipStream_t s) {
+  if (nnzb <= 0) return hipSuccess;
+  if (nnzb >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+  auto sz = [](size_t elem, size_t count) { return (elem * (count ? count : 1) + 255) / 256 * 256; };
+  const size_t E = (size_t)nnzb;
+  size_t cub_bytes = 0;
+  PD_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, cub_bytes, pos, (int64_t *)nullptr,
+                                            (const int32_t *)nullptr, order, (int)nnzb, 0,
+                                            bits_for(n_values), s));
+  void *q = nullptr;
+  PD_TRY(alloc(&q, sz(8, E) + sz(4, E) + sz(1, cub_bytes)));
+  char *base = static_cast<char *>(q);
+  int64_t *pos_s = reinterpret_cast<int64_t *>(base);
+  int32_t *iota = reinterpret_cast<int32_t *>(base + sz(8, E));
+  void *cub_tmp = base + sz(8, E) + sz(4, E);
+  hipLaunchKernelGGL(k_pd_iota, grid_for(nnzb), dim3(kT), 0, s, (int32_t)nnzb, iota);
+  PD_TRY(hipGetLastError());
+  return hipcub::DeviceRadixSort::SortPairs(cub_tmp, cub_bytes, pos, pos_s, iota, order, (int)nnzb,
+                                            0, bits_for(n_values), s);
+}
+
 }  // namespace vbcsr

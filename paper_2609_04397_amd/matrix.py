@@ -193,6 +193,7 @@ class Matrix:
             if v.size != self.n_values:
                 raise ValueError("expected %d values" % self.n_values)
             check(lib.vbcsr_set_values(self._h, v.ctypes.data, 0, 0, _stream()))
+        self._pages = None  # the library returned to the handle's own pages
         Matrix._stamps += 1
         self._stamp = Matrix._stamps
 
@@ -237,6 +238,56 @@ class Matrix:
         check(_lib.load().vbcsr_sddmm(self._h, _ptr(dY), dY.stride(0) if self.N_rows else dY.shape[1],
                                       _ptr(X), X.stride(0) if self.N else X.shape[1], X.shape[1],
                                       _ptr(out), _stream()))
+        return out
+
+    # -- values in the forward-page layout -----------------------------------
+    @property
+    def page_size(self):
+        """Entries of a page-layout value buffer (values at their forward-page
+        positions, zero alignment gaps and slack)."""
+        n = ctypes.c_int64()
+        check(_lib.load().vbcsr_page_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def _pages_arg(self, pages, name):
+        if not (isinstance(pages, torch.Tensor) and pages.is_cuda and pages.dtype == self.dtype
+                and pages.dim() == 1 and pages.is_contiguous() and pages.numel() == self.page_size):
+            raise ValueError("%s must be a contiguous CUDA %s tensor of %d entries"
+                             % (name, self.dtype, self.page_size))
+        return pages
+
+    def get_pages(self):
+        """The current forward values in the page layout (a new device tensor)."""
+        out = torch.empty(self.page_size, dtype=self.dtype, device=self.device)
+        check(_lib.load().vbcsr_get_pages(self._h, _ptr(out), _stream()))
+        return out
+
+    def use_pages(self, pages):
+        """Forward products read their values from ``pages`` (kept, not copied);
+        ``None`` returns to the handle's own pages.  The transposed pages are
+        stale until ``refresh_transposed``."""
+        if pages is not None:
+            self._pages_arg(pages, "pages")
+        check(_lib.load().vbcsr_use_pages(self._h, None if pages is None else _ptr(pages)))
+        self._pages = pages
+
+    def refresh_transposed(self):
+        """Rebuild the transposed pages from the current forward values."""
+        check(_lib.load().vbcsr_refresh_transposed(self._h, _stream()))
+
+    def sddmm_pages(self, dY, X, out=None):
+        """``sddmm`` written in the page layout (zeros in the gaps)."""
+        dY = self._vec(dY, "dY", self.N_rows)
+        X = self._vec(X, "X")
+        if dY.shape[1] != X.shape[1]:
+            raise ValueError("dY and X need the same number of columns")
+        if out is None:
+            out = torch.empty(self.page_size, dtype=self.dtype, device=X.device)
+        self._pages_arg(out, "out")
+        check(_lib.load().vbcsr_sddmm_pages(self._h, _ptr(dY),
+                                            dY.stride(0) if self.N_rows else dY.shape[1], _ptr(X),
+                                            X.stride(0) if self.N else X.shape[1], X.shape[1],
+                                            _ptr(out), _stream()))
         return out
 
     def cheb_workspace_bytes(self, nrhs, degree):
@@ -319,3 +370,38 @@ class _SpmmFunction(torch.autograd.Function):
 def spmm(values, X, A: Matrix):
     """Differentiable ``A(values) @ X`` (values in graph order)."""
     return _SpmmFunction.apply(values, X, A)
+
+
+class _SpmmPagesFunction(torch.autograd.Function):
+    """``Y = A(pages) X`` with the parameter in the forward-page layout
+    (``Matrix.get_pages``): the forward reads ``pages`` in place, with no
+    packing; the backward writes the gradient in the same layout
+    (block-sampled product at the pages' positions, zero gaps) and rebuilds
+    the transposed pages from ``pages`` only when ``dX`` is needed."""
+
+    @staticmethod
+    def forward(ctx, pages, X, A):
+        A.use_pages(pages)
+        Y = A.spmm(X)
+        ctx.A = A
+        ctx.save_for_backward(pages, X)
+        return Y
+
+    @staticmethod
+    def backward(ctx, G):
+        pages, X = ctx.saved_tensors
+        A = ctx.A
+        G = G.contiguous()
+        A.use_pages(pages)   # another forward may have pointed the handle elsewhere
+        dP = A.sddmm_pages(G, X) if ctx.needs_input_grad[0] else None
+        dX = None
+        if ctx.needs_input_grad[1]:
+            A.refresh_transposed()
+            dX = A.spmm_t(G)
+        return dP, dX, None
+
+
+def spmm_pages(pages, X, A: Matrix):
+    """Differentiable ``A(pages) @ X`` with the values held in the operator's
+    forward-page layout (``A.page_size`` entries, zero gaps)."""
+    return _SpmmPagesFunction.apply(pages, X, A)
