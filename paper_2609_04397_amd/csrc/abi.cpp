@@ -122,7 +122,8 @@ struct DevDir {
   int64_t *blk_pos = nullptr;
   int32_t *blk_k0 = nullptr;
   int32_t *blk_prow = nullptr;
-  int32_t *blk_order = nullptr;  // graph blocks in page order (FP64/FP32 packing)
+  PageRec *page_recs = nullptr;  // transposed only: block maps in page order (built on
+                                 // the first vbcsr_refresh_transposed)
   int64_t *colg = nullptr;    // forward direction only
   int64_t n_values = 0, n_values16 = 0;
   int32_t npanels = 0;        // forward: block rows; transposed: block columns
@@ -790,41 +791,44 @@ int vbcsr_refresh_transposed(vbcsr_mat *A, void *stream) try {
   if (int rc = vbcsr_page_size(A, &n)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   DevDir &D = A->dir[1];
-  if (A->nnz > 0 && !D.blk_order) {
-    // first call: the blocks in transposed-page order (the rebuild walks the
-    // pages it writes)
+  const int es = A->prec == VBCSR_FP64 ? 8 : 4;
+  if (A->nnz > 0 && !D.page_recs) {
+    // first call: the blocks' maps in transposed-page order (the rebuild
+    // walks the pages it writes)
+    PageRec *recs = nullptr;
     int rc;
-    if ((rc = alloc_into(A, &D.blk_order, (size_t)A->nnzb))) return rc;
+    if ((rc = dev_alloc(reinterpret_cast<void **>(&recs), sizeof(PageRec) * A->nnzb))) return rc;
     std::vector<void *> tmp;
     const DevAlloc alloc = [&](void **q, size_t bytes) -> hipError_t {
       if (dev_alloc(q, bytes) != VBCSR_OK) return hipErrorOutOfMemory;
       tmp.push_back(*q);
       return hipSuccess;
     };
-    hipError_t e = launch_page_order(D.blk_pos, A->nnzb, D.n_values, D.blk_order, alloc, s);
-    if (e == hipSuccess && !tmp.empty()) e = hipStreamSynchronize(s);
+    int32_t *order = nullptr;
+    hipError_t e = alloc(reinterpret_cast<void **>(&order), sizeof(int32_t) * A->nnzb);
+    if (e == hipSuccess) e = launch_page_order(D.blk_pos, A->nnzb, D.n_values, order, alloc, s);
+    if (e == hipSuccess) {
+      PackParams pp{};
+      pp.b = A->b;
+      pp.blk_row = A->blk_row;
+      pp.col_idx = A->col_idx;
+      pp.nnzb = A->nnzb;
+      pp.dir[0].pos = A->dir[0].blk_pos;
+      pp.dir[1].pos = D.blk_pos;
+      e = launch_refresh_records(pp, order, recs, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     for (void *q : tmp) (void)hipFree(q);
     if (e != hipSuccess) {
-      D.blk_order = nullptr;   // still owned by the handle, freed with it
-      return hip_fail(e, "page order");
+      (void)hipFree(recs);
+      return hip_fail(e, "page records");
     }
+    A->owned.push_back(recs);
+    D.page_recs = recs;
   }
   if (A->nnz > 0) {
-    PackParams pp{};
-    pp.b = A->b;
-    pp.blk_row = A->blk_row;
-    pp.col_idx = A->col_idx;
-    pp.gbase = A->gbase;
-    pp.nnzb = A->nnzb;
-    pp.dst_kind = A->prec == VBCSR_FP64 ? 0 : 1;
-    for (int d = 0; d < 2; ++d) {
-      pp.dir[d].pos = A->dir[d].blk_pos;
-      pp.dir[d].k0 = A->dir[d].blk_k0;
-      pp.dir[d].prow = A->dir[d].blk_prow;
-    }
-    pp.dir[1].dst = A->dir[1].vals;
-    hipError_t e = launch_pack_dst(pp, D.blk_order, 1, A->dir[0].vals, 2, s);
-    if (e != hipSuccess) return hip_fail(e, "pack kernel launch");
+    hipError_t e = launch_refresh(D.page_recs, A->nnzb, es, A->dir[0].vals, D.vals, s);
+    if (e != hipSuccess) return hip_fail(e, "refresh kernel launch");
   }
   A->tr_stale = false;
   return VBCSR_OK;

@@ -1064,10 +1064,7 @@ struct PackRec {       // one block of a run, in LDS
 };
 static_assert(sizeof(PackRec) == 64, "PackRec layout");
 
-// SRC 0/1: double / float source in graph order, both page sets written;
-// SRC 2: the forward pages (of the page type) as source, only the transposed
-// pages written.  KIND: dst_kind.
-template <int SRC, int KIND>
+template <int SRC, int KIND>  // SRC 0/1: double/float source; KIND: dst_kind
 __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src) {
   __shared__ PackRec tab_all[kWaves * kPackRun];
   const int64_t k0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
@@ -1106,9 +1103,8 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
   const int len = __builtin_amdgcn_readlane(start + n, nb - 1);
 #pragma unroll
   for (int u = 0; u < kPackRun; ++u) st[u] = u < nb ? __builtin_amdgcn_readlane(start, u) : len;
-  // SRC 2: the source is the forward pages, of the destination type
   auto load = [&](int64_t at) {
-    if constexpr (SRC == 0 || (SRC == 2 && KIND == 0))
+    if constexpr (SRC == 0)
       return static_cast<const double *>(src)[at];
     else
       return (double)static_cast<const float *>(src)[at];
@@ -1146,18 +1142,14 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
         qq[c] = q;
         // row-major sweep: the source is read in its own order (the load
         // does not wait on the block lookup)
-        v[c] = SRC == 2 ? load(rt.pf + (int64_t)q * b1 + p)
-                        : load(g0 + (sweep == 0 ? (int64_t)ec
-                                                : (int64_t)rt.start + (int64_t)p * b2 + q));
+        v[c] = load(g0 + (sweep == 0 ? (int64_t)ec : (int64_t)rt.start + (int64_t)p * b2 + q));
       }
 #pragma unroll
       for (int c = 0; c < kPackChunk; ++c) {
         if (e0 + 64 * c >= len) break;
         const PackRec &rt = tab[tt[c]];
         const int b1 = rt.bi, b2 = rt.bj, p = pp[c], q = qq[c];
-        if (SRC == 2) {
-          pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v[c]);
-        } else if (KIND != 2) {
+        if (KIND != 2) {
           // transposed panel of atom j: height b_j, row q, column k0 + p
           pack_store(P.dir[1], KIND, rt.pt, 0, 0, b2, q, p, v[c]);
           // forward panel of atom i: height b_i, row p, column k0 + q
@@ -1172,39 +1164,39 @@ __global__ void __launch_bounds__(kThreads) k_pack(PackParams P, const void *src
   }
 }
 
-// Value packing in the order of the pages written: one wave per run of
-// kPackRun consecutive blocks of direction DIR's page order (`order`), whose
-// destination values are contiguous apart from the alignment gap between two
-// panels, so stores form whole contiguous runs whatever the block sizes (in
-// source order, neighbouring small blocks land in different panels and their
-// lines are written in pieces by different waves).  Lane l takes elements
-// l, l + 64, ... of the run in destination order; sources: SRC 0 / 1 graph
-// order (double / float, row-major blocks), SRC 2 the forward pages
-// (column-major blocks, of the page type).  DIR 0 writes the forward pages
-// (column-major blocks), DIR 1 the transposed pages (row-major blocks).
-template <int SRC, int KIND, int DIR>   // KIND 0 / 1: double / float pages
-__global__ void __launch_bounds__(kThreads) k_pack_dst(PackParams P, const int32_t *order,
-                                                       const void *src) {
-  using T = typename std::conditional<KIND == 0, double, float>::type;
-  __shared__ int32_t tab_b[kWaves * kPackRun * 2];
-  __shared__ int64_t tab_p[kWaves * kPackRun * 2];
+// Rebuild of the transposed pages from the forward pages, walking the
+// transposed pages: rec[u] describes the block at transposed-page position u
+// (its forward-page and transposed-page offsets and its shape), so a wave
+// reads its run's maps with one load per lane before its element loads.
+__global__ void __launch_bounds__(kThreads) k_refresh_records(PackParams P, const int32_t *order,
+                                                              PageRec *rec) {
+  const int64_t u = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (u >= P.nnzb) return;
+  const int32_t k = order[u];
+  PageRec r;
+  r.src = P.dir[0].pos[k];
+  r.dst = P.dir[1].pos[k];
+  r.bi = P.b[P.blk_row[k]];
+  r.bj = P.b[P.col_idx[k]];
+  r.pad[0] = r.pad[1] = 0;
+  rec[u] = r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_refresh(const PageRec *rec, int64_t nnzb,
+                                                      const T *src, T *dst) {
+  __shared__ PageRec tab_all[kWaves * kPackRun];
   const int64_t u0 = ((int64_t)blockIdx.x * kWaves + wave_id()) * kPackRun;
-  if (u0 >= P.nnzb) return;
+  if (u0 >= nnzb) return;
   const int lane = threadIdx.x & 63;
-  const int nb = (int)min((int64_t)kPackRun, P.nnzb - u0);
-  int32_t *tb = tab_b + wave_id() * kPackRun * 2;
-  int64_t *tp = tab_p + wave_id() * kPackRun * 2;
+  const int nb = (int)min((int64_t)kPackRun, nnzb - u0);
+  PageRec *tab = tab_all + wave_id() * kPackRun;
   int n = 0;
   if (lane < nb) {
-    const int32_t k = order[u0 + lane];
-    const int bi = P.b[P.blk_row[k]], bj = P.b[P.col_idx[k]];
-    n = bi * bj;
-    tb[2 * lane] = bi;
-    tb[2 * lane + 1] = bj;
-    tp[2 * lane] = SRC == 2 ? P.dir[0].pos[k] : P.gbase[k];
-    tp[2 * lane + 1] = P.dir[DIR].pos[k];
+    const PageRec r = rec[u0 + lane];
+    n = r.bi * r.bj;
+    tab[lane] = r;
   }
-  // run-relative first value of each block: exclusive prefix sum of n
   int incl = n;
 #pragma unroll
   for (int o = 1; o < kPackRun; o <<= 1) {
@@ -1217,15 +1209,12 @@ __global__ void __launch_bounds__(kThreads) k_pack_dst(PackParams P, const int32
   const int len = __builtin_amdgcn_readlane(incl, nb - 1);
 #pragma unroll
   for (int u = 0; u < kPackRun; ++u) st[u] = u < nb ? __builtin_amdgcn_readlane(start, u) : len;
-  T *dst = static_cast<T *>(P.dir[DIR].dst);
-  // chunks of kPackChunk elements per lane: all loads before the stores
   for (int e0 = lane; e0 < len; e0 += 64 * kPackChunk) {
     T v[kPackChunk];
     int64_t d[kPackChunk];
 #pragma unroll
     for (int c = 0; c < kPackChunk; ++c) {
       const int e = min(e0 + 64 * c, len - 1);
-      // the block of element e (starts ascending, st[0] = 0) and its first value
       int t = 0, stt = 0;
 #pragma unroll
       for (int u = 1; u < kPackRun; ++u)
@@ -1233,27 +1222,14 @@ __global__ void __launch_bounds__(kThreads) k_pack_dst(PackParams P, const int32
           t = u;
           stt = st[u];
         }
-      const int b1 = tb[2 * t], b2 = tb[2 * t + 1];
-      const int l = e - stt;
-      // destination element (p, q) of the b1 x b2 block
-      int p, q;
-      if (DIR == 1) {   // row-major: p = l / b2
-        p = (int)((float)l * __builtin_amdgcn_rcpf((float)b2));
-        q = l - p * b2;
-        if (q >= b2) { ++p; q -= b2; }
-      } else {          // column-major: q = l / b1
-        q = (int)((float)l * __builtin_amdgcn_rcpf((float)b1));
-        p = l - q * b1;
-        if (p >= b1) { ++q; p -= b1; }
-      }
-      const int64_t so = tp[2 * t] + (SRC == 2 ? (int64_t)q * b1 + p : (int64_t)p * b2 + q);
-      if constexpr (SRC == 0)
-        v[c] = (T) static_cast<const double *>(src)[so];
-      else if constexpr (SRC == 1)
-        v[c] = (T) static_cast<const float *>(src)[so];
-      else
-        v[c] = static_cast<const T *>(src)[so];
-      d[c] = tp[2 * t + 1] + l;
+      const PageRec &r = tab[t];
+      const int b1 = r.bi, b2 = r.bj, l = e - stt;
+      // element (p, q): row-major at the destination, column-major at the source
+      int p = (int)((float)l * __builtin_amdgcn_rcpf((float)b2));
+      int q = l - p * b2;
+      if (q >= b2) { ++p; q -= b2; }
+      v[c] = src[r.src + (int64_t)q * b1 + p];
+      d[c] = r.dst + l;
     }
 #pragma unroll
     for (int c = 0; c < kPackChunk; ++c) {
@@ -2084,8 +2060,6 @@ hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipS
     case 3: hipLaunchKernelGGL((k_pack<1, 0>), grid, dim3(kThreads), 0, s, p, src); break;
     case 4: hipLaunchKernelGGL((k_pack<1, 1>), grid, dim3(kThreads), 0, s, p, src); break;
     case 5: hipLaunchKernelGGL((k_pack<1, 2>), grid, dim3(kThreads), 0, s, p, src); break;
-    case 6: hipLaunchKernelGGL((k_pack<2, 0>), grid, dim3(kThreads), 0, s, p, src); break;
-    case 7: hipLaunchKernelGGL((k_pack<2, 1>), grid, dim3(kThreads), 0, s, p, src); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -2186,25 +2160,25 @@ hipError_t launch_block_norms(const double *pages, const int64_t *pos, const int
   return hipGetLastError();
 }
 
-hipError_t launch_pack_dst(const PackParams &p, const int32_t *order, int dir, const void *src,
-                           int src_dtype, hipStream_t s) {
+hipError_t launch_refresh_records(const PackParams &p, const int32_t *order, PageRec *rec,
+                                  hipStream_t s) {
   if (p.nnzb == 0) return hipSuccess;
-  const int64_t waves = (p.nnzb + kPackRun - 1) / kPackRun;
+  hipLaunchKernelGGL(k_refresh_records, dim3((unsigned)((p.nnzb + kThreads - 1) / kThreads)),
+                     dim3(kThreads), 0, s, p, order, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_refresh(const PageRec *rec, int64_t nnzb, int elem_bytes, const void *src,
+                          void *dst, hipStream_t s) {
+  if (nnzb == 0) return hipSuccess;
+  const int64_t waves = (nnzb + kPackRun - 1) / kPackRun;
   const dim3 grid((unsigned)((waves + kWaves - 1) / kWaves));
-  const int sel = (src_dtype * 2 + p.dst_kind) * 2 + dir;
-  switch (sel) {
-    case 0: hipLaunchKernelGGL((k_pack_dst<0, 0, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 1: hipLaunchKernelGGL((k_pack_dst<0, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 2: hipLaunchKernelGGL((k_pack_dst<0, 1, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 3: hipLaunchKernelGGL((k_pack_dst<0, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 4: hipLaunchKernelGGL((k_pack_dst<1, 0, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 5: hipLaunchKernelGGL((k_pack_dst<1, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 6: hipLaunchKernelGGL((k_pack_dst<1, 1, 0>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 7: hipLaunchKernelGGL((k_pack_dst<1, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 9: hipLaunchKernelGGL((k_pack_dst<2, 0, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    case 11: hipLaunchKernelGGL((k_pack_dst<2, 1, 1>), grid, dim3(kThreads), 0, s, p, order, src); break;
-    default: return hipErrorInvalidValue;
-  }
+  if (elem_bytes == 8)
+    hipLaunchKernelGGL(k_refresh<double>, grid, dim3(kThreads), 0, s, rec, nnzb,
+                       static_cast<const double *>(src), static_cast<double *>(dst));
+  else
+    hipLaunchKernelGGL(k_refresh<float>, grid, dim3(kThreads), 0, s, rec, nnzb,
+                       static_cast<const float *>(src), static_cast<float *>(dst));
   return hipGetLastError();
 }
 

@@ -69,15 +69,24 @@ struct PackParams {
   int dst_kind;             // 0 = double pages, 1 = float pages, 2 = BF16 hi/lo pages
   PackDir dir[2];           // 0: forward panels (column-major blocks), 1: transposed
 };
-// src_dtype 0 / 1: graph-order double / float source, both page sets written;
-// 2: the forward pages (dst_kind 0 or 1) as source, only the transposed pages
-// (dir[1]) written.
+// src_dtype 0 / 1: graph-order double / float source, both page sets written.
 hipError_t launch_pack(const PackParams &p, const void *src, int src_dtype, hipStream_t s);
-// One page set (dir 0 forward, 1 transposed; dst_kind 0 or 1) written in its
-// own order: order[u] = graph block at page-order position u of direction
-// dir.  src_dtype as launch_pack (2 only with dir 1).
-hipError_t launch_pack_dst(const PackParams &p, const int32_t *order, int dir, const void *src,
-                           int src_dtype, hipStream_t s);
+// Map of one block at a transposed-page position: forward-page offset
+// (column-major block) and transposed-page offset (row-major block) of its
+// first value, and its shape.
+struct PageRec {
+  int64_t src, dst;
+  int32_t bi, bj;
+  int32_t pad[2];
+};
+static_assert(sizeof(PageRec) == 32, "PageRec layout");
+// rec[u] for the graph block order[u] (u < nnzb), from the packing maps.
+hipError_t launch_refresh_records(const PackParams &p, const int32_t *order, PageRec *rec,
+                                  hipStream_t s);
+// Transposed pages (dst) rebuilt from the forward pages (src), elem_bytes 8
+// or 4, walking the transposed pages through rec.
+hipError_t launch_refresh(const PageRec *rec, int64_t nnzb, int elem_bytes, const void *src,
+                          void *dst, hipStream_t s);
 // order[u] = graph block whose position pos[block] is the u-th smallest
 // (page order of one direction; positions are distinct, below n_values).
 hipError_t launch_page_order(const int64_t *pos, int64_t nnzb, int64_t n_values, int32_t *order,
