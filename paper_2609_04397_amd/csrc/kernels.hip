@@ -1489,7 +1489,9 @@ __global__ void __launch_bounds__(kThreads) k_sddmm_lds(SddmmParams<T> P) {
 // hit 16 distinct bank groups.  Lane l reads the X row indices of its four
 // rows with one 16-byte load (rows past the panel are not loaded).  Column indices and output maps are loaded two tiles ahead.
 // Requires X within 2^31 bytes (one buffer descriptor).
-template <int NCH>
+// PAGE: outputs in the forward pages' layout (P.page_out), where a tile's
+// outputs are one contiguous run and nothing is held back.
+template <int NCH, bool PAGE>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sddmm_dma(SddmmParams<double> P) {
   using LdsPtr = __attribute__((address_space(3))) void *;
   constexpr int CW = 32;
@@ -1519,7 +1521,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   };
   auto gmap_of = [&](int j) {
     const int kk = min(j * 16 + m, K - 1);
-    return P.page_out ? page_map(rd, kk) : cg[kk];
+    return PAGE ? page_map(rd, kk) : cg[kk];
   };
   const int sslot = lane & 15;
   auto issue = [&](int s, v4u32 xr) {
@@ -1597,7 +1599,7 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
             const uint32_t u15 = __shfl(u, 15, 64);
             const uint32_t unext = (uint32_t)(__shfl(g_cur, 0, 64) >> 7);
             const uint32_t brks = (uint32_t)__ballot(brk) & 0xFFFFu;
-            const int split = unext == u15 + 1u ? 31 - __builtin_clz(brks) : 16;
+            const int split = !PAGE && unext == u15 + 1u ? 31 - __builtin_clz(brks) : 16;
             if (m >= csplit) {
               const int64_t base = g_carry >> 7;
               const int bj = (int)(g_carry & 127);
@@ -2073,10 +2075,14 @@ hipError_t launch_sddmm_t(const SddmmParams<T> &p, hipStream_t s) {
   if (p.xrows * p.ldx * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
     if (std::is_same<T, double>::value && (p.nrhs == 32 || p.nrhs == 64)) {
       const auto &pd = reinterpret_cast<const SddmmParams<double> &>(p);
-      if (p.nrhs == 32)
-        hipLaunchKernelGGL((k_sddmm_dma<1>), grid, dim3(kThreads), 0, s, pd);
+      if (p.nrhs == 32 && p.page_out)
+        hipLaunchKernelGGL((k_sddmm_dma<1, true>), grid, dim3(kThreads), 0, s, pd);
+      else if (p.nrhs == 32)
+        hipLaunchKernelGGL((k_sddmm_dma<1, false>), grid, dim3(kThreads), 0, s, pd);
+      else if (p.page_out)
+        hipLaunchKernelGGL((k_sddmm_dma<2, true>), grid, dim3(kThreads), 0, s, pd);
       else
-        hipLaunchKernelGGL((k_sddmm_dma<2>), grid, dim3(kThreads), 0, s, pd);
+        hipLaunchKernelGGL((k_sddmm_dma<2, false>), grid, dim3(kThreads), 0, s, pd);
       return hipGetLastError();
     }
     if (p.nrhs <= 32)
