@@ -480,7 +480,8 @@ int create_impl(vbcsr_mat **out, int32_t n_atoms, const int32_t *block_sizes,
 // (row pointer d_rp, n + 1 entries; columns d_ci, ascending within each row)
 // with graph-order values d_vals (n_values of them): planned on the device in
 // the processing order d_order (a permutation of the atoms), so the pattern
-// never passes through the host.
+// never passes through the host.  d_vals null: the pages are left for the
+// caller to fill (their gaps are zero).
 int create_planned_on_device(vbcsr_mat **out, const vbcsr_mat *A, int64_t nnzb, int64_t n_values,
                              const int64_t *d_rp, const int32_t *d_ci, const double *d_vals,
                              const int32_t *d_order, const vbcsr_plan_opts *opts,
@@ -555,7 +556,7 @@ int create_planned_on_device(vbcsr_mat **out, const vbcsr_mat *A, int64_t nnzb, 
     D.npanels = n;
     if ((rc = finish_direction(C, d, po.dir[d].n_cols, s))) return rc;
   }
-  if (C->nnz > 0 && (rc = pack_all(C, d_vals, 0, s))) return rc;
+  if (C->nnz > 0 && d_vals && (rc = pack_all(C, d_vals, 0, s))) return rc;
   HIP_TRY(hipStreamSynchronize(s), "spgemm");
   *out = C;
   C = nullptr;  // owned by the caller now
@@ -1281,10 +1282,56 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   sp.avals = static_cast<const double *>(A->dir[1].vals);
   sp.bvals = static_cast<const double *>(B->dir[0].vals);
   sp.b = A->b;
+  // C is laid out on the device in A's processing order (row order AUTO) or
+  // in atom order; an RCM or cluster order of C's own graph comes from the
+  // host planner, which takes the pattern back.  Without a final filter
+  // (eps = 0) a device layout comes first and the numeric stage writes C's
+  // two page sets directly.
+  vbcsr_plan_opts copts{};
+  if (opts) copts = *opts;
+  const int32_t c_order = copts.row_order;
+  const bool device_layout = c_order == VBCSR_ORDER_AUTO || c_order == VBCSR_ORDER_ATOM;
+  const bool direct = device_layout && eps == 0.0;
   double *cvals = nullptr, *cnorm = nullptr;
-  if ((rc = tmp.alloc(&cvals, (size_t)nvals)) || (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
+  if ((!direct && (rc = tmp.alloc(&cvals, (size_t)nvals))) ||
+      (eps > 0.0 && (rc = tmp.alloc(&cnorm, (size_t)nC))))
     return rc;
   st.ms_symbolic = ms_since(t0);
+  auto processing_order = [&](int32_t **d_ord) -> int {
+    int r;
+    if ((r = tmp.alloc(d_ord, (size_t)std::max<int32_t>(n, 1)))) return r;
+    hipError_t e2 = c_order == VBCSR_ORDER_ATOM
+                        ? launch_iota(n, *d_ord, s)
+                        : launch_order_from_rows(A->dir[0].rows, A->dir[0].npanels, A->off, n,
+                                                 *d_ord, s);
+    return e2 == hipSuccess ? VBCSR_OK : hip_fail(e2, "order kernel launch");
+  };
+  // C's handle until it is returned (freed on every failure after it exists)
+  struct CGuard {
+    vbcsr_mat **h;
+    bool keep = false;
+    ~CGuard() {
+      if (!keep && *h) {
+        free_all(*h);
+        delete *h;
+        *h = nullptr;
+      }
+    }
+  } cguard{out};
+  if (direct) {
+    t0 = clk::now();
+    int32_t *d_ord = nullptr;
+    if ((rc = processing_order(&d_ord))) return rc;
+    rc = create_planned_on_device(out, A, nC, nvals, so.crp, so.oj, nullptr, d_ord, &copts,
+                                  dalloc, s);
+    if (alloc_rc != VBCSR_OK) return alloc_rc;
+    if (rc) return rc;
+    st.ms_build = ms_since(t0);
+    sp.fpages = static_cast<double *>((*out)->dir[0].vals);
+    sp.tpages = static_cast<double *>((*out)->dir[1].vals);
+    sp.fpos = (*out)->dir[0].blk_pos;
+    sp.tpos = (*out)->dir[1].blk_pos;
+  }
   sp.oi = so.oi;
   sp.oj = so.oj;
   sp.obase = so.obase;
@@ -1318,6 +1365,12 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   (void)hipEventDestroy(ev[1]);
   if (e != hipSuccess) return hip_fail(e, "numeric stage");
   st.ms_numeric = ms;
+  if (direct) {   // C is complete
+    st.nnzb = nC;
+    cguard.keep = true;
+    if (stats) *stats = st;
+    return VBCSR_OK;
+  }
 
   // closing norm filter on the device: drop computed blocks whose norm is
   // below eps (the pattern of C, its row pointer and values stay on the device)
@@ -1342,21 +1395,11 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   st.nnzb = c_nnzb;
   st.ms_filter = ms_since(t0);
 
-  // C as an ordinary handle over the same atoms: laid out on the device in
-  // A's processing order (row order AUTO) or in atom order; an RCM or
-  // cluster order of C's own graph comes from the host planner, which takes
-  // the pattern back
+  // C as an ordinary handle over the same atoms
   t0 = clk::now();
-  vbcsr_plan_opts copts{};
-  if (opts) copts = *opts;
-  const int32_t c_order = copts.row_order;
-  if (c_order == VBCSR_ORDER_AUTO || c_order == VBCSR_ORDER_ATOM) {
+  if (device_layout) {
     int32_t *d_ord = nullptr;
-    if ((rc = tmp.alloc(&d_ord, (size_t)std::max<int32_t>(n, 1)))) return rc;
-    e = c_order == VBCSR_ORDER_ATOM
-            ? launch_iota(n, d_ord, s)
-            : launch_order_from_rows(A->dir[0].rows, A->dir[0].npanels, A->off, n, d_ord, s);
-    if (e != hipSuccess) return hip_fail(e, "order kernel launch");
+    if ((rc = processing_order(&d_ord))) return rc;
     rc = create_planned_on_device(out, A, c_nnzb, final_nvals, c_rp, c_ci, final_vals, d_ord,
                                   &copts, dalloc, s);
     if (alloc_rc != VBCSR_OK) return alloc_rc;
@@ -1371,6 +1414,7 @@ int vbcsr_spgemm(vbcsr_mat **out, const vbcsr_mat *A, const vbcsr_mat *B, double
   }
   if (rc) return rc;
   st.ms_build = ms_since(t0);
+  cguard.keep = true;
   if (stats) *stats = st;
   return VBCSR_OK;
 } catch (...) {

@@ -1878,6 +1878,24 @@ __device__ __forceinline__ void spgemm_tiles(const SpgemmParams &P, int64_t c, i
       }
     }
   }
+  if (P.fpages) {   // straight into C's pages: forward column-major, transposed row-major
+    double *of = P.fpages + P.fpos[c];
+    double *ot = P.tpages + P.tpos[c];
+#pragma unroll
+    for (int ti = 0; ti < TI; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < TJ; ++tj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = (ti0 + ti) * 16 + dst_row<double>(kq, e), col = (tj0 + tj) * 16 + m;
+          if (r < bi && col < bj) {
+            ot[(int64_t)r * bj + col] = acc[ti][tj][e];
+            of[(int64_t)col * bi + r] = acc[ti][tj][e];
+            ss = fma(acc[ti][tj][e], acc[ti][tj][e], ss);
+          }
+        }
+    return;
+  }
   double *out = P.cvals + P.obase[c];
 #pragma unroll
   for (int ti = 0; ti < TI; ++ti)

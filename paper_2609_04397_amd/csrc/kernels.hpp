@@ -143,8 +143,12 @@ struct SpgemmParams {
   const int64_t *pb;
   const int32_t *order;
   int64_t count;
-  double *cvals;
+  double *cvals;          // C in graph order at obase (when fpages is null)
   double *cnorm;
+  // C's own pages (when not null): block c at fpos[c] of the forward pages
+  // (column-major) and at tpos[c] of the transposed pages (row-major)
+  double *fpages, *tpages;
+  const int64_t *fpos, *tpos;
 };
 // Tile class of a b_i x b_j block: 0 (1x1 tiles of 16), 1 (1x2), 2 (2x1),
 // 3 (2x2), 4 (anything larger).
