@@ -267,6 +267,13 @@ def test_null_handle_and_bad_arguments(lib):
     assert lib.vbcsr_spgemm(ctypes.byref(out), None, None, 0.0, None, None, None) == _lib.VBCSR_EINVAL
     assert out.value is None
     assert lib.vbcsr_spgemm(None, None, None, 0.0, None, None, None) == _lib.VBCSR_EINVAL
+    # page-layout calls
+    n = ctypes.c_int64(-1)
+    assert lib.vbcsr_page_size(None, ctypes.byref(n)) == _lib.VBCSR_EINVAL and n.value == -1
+    assert lib.vbcsr_get_pages(None, None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_use_pages(None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_refresh_transposed(None, None) == _lib.VBCSR_EINVAL
+    assert lib.vbcsr_sddmm_pages(None, None, 1, None, 1, 1, None, None) == _lib.VBCSR_EINVAL
     lib.vbcsr_destroy(None)
     h = ctypes.c_void_p()
     b = np.array([1], np.int32)
