@@ -27,7 +27,11 @@ Timed alongside, each in a loop of its own with the same protocol:
              and plain FP64, and their ratio;
   c2_step    the 32^3 simple-cubic lattice (b = 13): SpMV, SpMM/SpMM^T/SDDMM
              at nrhs 32 and one Chebyshev step in FP64, FP32 and BF16x3 at
-             nrhs 64 on the scaled operator.
+             nrhs 64 on the scaled operator;
+  spgemm     the thresholded block product A A of the 11,520-atom operator
+             with b in 9..20 (G1) at eps 0 and 1: whole call (host clock,
+             median of 3 after 1) and its phases (the same records as
+             --spgemm, without the oracle).
 
 Timing: W untimed warm-up steps, then K steps bracketed by device
 synchronisation; every call is also bracketed by HIP events on the stream
@@ -84,7 +88,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sections", default="c3,precision,fwd_bwd,c2",
+    ap.add_argument("--sections", default="c3,precision,fwd_bwd,c2,spgemm",
                     help="comma list of timed sections (c3 is the headline)")
     ap.add_argument("--only", default="", help="comma list of rows to run (profiling)")
     ap.add_argument("--no-cpu", action="store_true",
@@ -466,6 +470,9 @@ def main():
     if "c2" in sections:
         print("bench: c2 section", file=sys.stderr, flush=True)
         out["c2_step"] = run_c2(args, checks, only)
+    if "spgemm" in sections:
+        print("bench: spgemm section", file=sys.stderr, flush=True)
+        out["spgemm"] = spgemm_records(with_cpu=False)
     if args.calib:
         out["copy_calib"] = copy_calibration()
     out["device"] = device_info()
