@@ -35,6 +35,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u __attribute__((ext_vector_type(8)));
 typedef unsigned int v4u32 __attribute__((ext_vector_type(4)));
+typedef unsigned int v2u32 __attribute__((ext_vector_type(2)));
 
 // Index of the calling wave in its workgroup.  The shift is the same for all
 // lanes of a wave, but the compiler cannot see that; reading it from the
@@ -1879,21 +1880,42 @@ __device__ __forceinline__ void spgemm_tiles(const SpgemmParams &P, int64_t c, i
     }
   }
   if (P.fpages) {   // straight into C's pages: forward column-major, transposed row-major
-    double *of = P.fpages + P.fpos[c];
+    // the forward (column-major) stores go through a wave-private LDS copy
+    // of the tile, so that 8 lanes write one whole column of 16 rows with
+    // 16-byte stores (a lane's own values are rows 4 apart of one column)
+    __shared__ __align__(16) double tl_all[kWaves * 16 * 18];
+    double *tl = tl_all + wave_id() * 16 * 18;   // column-major, 18 per column
     double *ot = P.tpages + P.tpos[c];
+    // the block's forward values: columns past b_j fall outside and are dropped
+    const __amdgpu_buffer_rsrc_t rf =
+        panel_rsrc(P.fpages + P.fpos[c], (uint32_t)(bi * bj) * 8u);
 #pragma unroll
     for (int ti = 0; ti < TI; ++ti)
 #pragma unroll
-      for (int tj = 0; tj < TJ; ++tj)
+      for (int tj = 0; tj < TJ; ++tj) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int r = (ti0 + ti) * 16 + dst_row<double>(kq, e), col = (tj0 + tj) * 16 + m;
           if (r < bi && col < bj) {
             ot[(int64_t)r * bj + col] = acc[ti][tj][e];
-            of[(int64_t)col * bi + r] = acc[ti][tj][e];
             ss = fma(acc[ti][tj][e], acc[ti][tj][e], ss);
           }
+          tl[m * 18 + dst_row<double>(kq, e)] = acc[ti][tj][e];
         }
+        wave_lds_sync();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int cl = 8 * h + (lane >> 3), rl = 2 * (lane & 7);
+          const int col = (tj0 + tj) * 16 + cl, r = (ti0 + ti) * 16 + rl;
+          const double2 v = *reinterpret_cast<const double2 *>(tl + cl * 18 + rl);
+          const uint32_t off = (uint32_t)(col * bi + r) * 8u;
+          if (r + 1 < bi)
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u32, v), rf, off, 0, 0);
+          else if (r < bi)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u32, v.x), rf, off, 0, 0);
+        }
+        wave_lds_sync();   // read before the next tile is written
+      }
     return;
   }
   double *out = P.cvals + P.obase[c];
