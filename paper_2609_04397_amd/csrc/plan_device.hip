@@ -59,14 +59,14 @@ __global__ void __launch_bounds__(kT) k_pd_rank(int32_t n, const int32_t *order,
 __global__ void __launch_bounds__(kT) k_pd_keys(int64_t nnzb, int d, const int32_t *blk_row,
                                                 const int32_t *ci, const int32_t *rank,
                                                 const int32_t *b, uint64_t *key, int32_t *val,
-                                                int32_t *width) {
+                                                unsigned long long *width) {
   const int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (k >= nnzb) return;
   const int32_t r = d == 0 ? blk_row[k] : ci[k];
   const int32_t c = d == 0 ? ci[k] : blk_row[k];
   key[k] = (uint64_t)(uint32_t)rank[r] << 7 | (uint32_t)b[c];
   val[k] = (int32_t)k;
-  atomicAdd(&width[r], b[c]);
+  atomicAdd(&width[r], (unsigned long long)b[c]);
 }
 
 // member widths in sorted order (entry nnzb = 0: the scan's total)
@@ -85,12 +85,12 @@ __global__ void __launch_bounds__(kT) k_pd_memberw(int64_t nnzb, int d, const in
 // per panel in processing order: width, value count and value count rounded
 // up to kPanelAlign; entry n = 0
 __global__ void __launch_bounds__(kT) k_pd_psize(int32_t np, const int32_t *order, const int32_t *b,
-                                                 const int32_t *width, int64_t *pk, int64_t *pv,
-                                                 int64_t *pu) {
+                                                 const unsigned long long *width, int64_t *pk,
+                                                 int64_t *pv, int64_t *pu) {
   const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (p < np) {
     const int32_t r = order[p];
-    const int64_t K = width[r];
+    const int64_t K = (int64_t)width[r];
     pk[p] = K;
     pu[p] = (int64_t)b[r] * K;
     pv[p] = ((int64_t)b[r] * K + kPanelAlign - 1) / kPanelAlign * kPanelAlign;
@@ -103,15 +103,16 @@ __global__ void __launch_bounds__(kT) k_pd_psize(int32_t np, const int32_t *orde
 
 __global__ void __launch_bounds__(kT) k_pd_rowdesc(int32_t np, const int32_t *order,
                                                    const int32_t *b, const int32_t *off,
-                                                   const int32_t *width, const int64_t *cb,
-                                                   const int64_t *vb, RowDesc *rows) {
+                                                   const unsigned long long *width,
+                                                   const int64_t *cb, const int64_t *vb,
+                                                   RowDesc *rows) {
   const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
   if (p >= np) return;
   const int32_t r = order[p];
   RowDesc rd;
   rd.vbase = vb[p];
   rd.cbase = cb[p];
-  rd.K = width[r];
+  rd.K = (int32_t)width[r];   // below 2^28 once the panel limit is checked
   rd.yrow = off[r];
   rd.b = b[r];
   rd.pad = 0;
@@ -241,8 +242,8 @@ hipError_t plan_device(const DevPlanIn &in, DevPlanOut &out, const DevAlloc &all
   // one allocation for every array (sizes are exact), one for hipCUB
   auto sz = [](size_t elem, size_t count) { return (elem * (count ? count : 1) + 255) / 256 * 256; };
   const size_t E = (size_t)nnzb, N1 = (size_t)n + 1;
-  const size_t total = 2 * sz(8, E) + 2 * sz(4, E) + 3 * sz(8, E + 1) + 2 * sz(4, N1) +
-                       5 * sz(8, N1) + sz(8, 2) + sz(4, kShapeSide * kShapeSide);
+  const size_t total = 2 * sz(8, E) + 2 * sz(4, E) + 3 * sz(8, E + 1) + sz(4, N1) +
+                       6 * sz(8, N1) + sz(8, 2) + sz(4, kShapeSide * kShapeSide);
   char *base = nullptr;
   {
     void *q = nullptr;
@@ -256,7 +257,8 @@ hipError_t plan_device(const DevPlanIn &in, DevPlanOut &out, const DevAlloc &all
     used += sz(sizeof(T), count);
   };
   uint64_t *key = nullptr, *key_s = nullptr;
-  int32_t *val = nullptr, *val_s = nullptr, *rank = nullptr, *width = nullptr;
+  int32_t *val = nullptr, *val_s = nullptr, *rank = nullptr;
+  unsigned long long *width = nullptr;
   int64_t *gsize = nullptr, *w = nullptr, *cpos = nullptr, *pk = nullptr, *pv = nullptr,
           *pu = nullptr, *cb = nullptr, *vb = nullptr, *mx = nullptr;
   unsigned int *hist = nullptr;
@@ -307,7 +309,7 @@ hipError_t plan_device(const DevPlanIn &in, DevPlanOut &out, const DevAlloc &all
   int64_t host[3 * 2];
   for (int d = 0; d < 2; ++d) {
     DevPlanDir &D = out.dir[d];
-    PD_TRY(hipMemsetAsync(width, 0, sizeof(int32_t) * N1, s));
+    PD_TRY(hipMemsetAsync(width, 0, sizeof(unsigned long long) * N1, s));
     if (nnzb > 0) {
       hipLaunchKernelGGL(k_pd_keys, grid_for(nnzb), dim3(kT), 0, s, nnzb, d, out.blk_row, in.ci,
                          rank, in.b, key, val, width);

@@ -166,3 +166,21 @@ def test_bf16x3_has_no_page_layout():
     A = Matrix.from_operator(op, prec="bf16x3")
     with pytest.raises(VbcsrError):
         A.page_size
+
+
+def test_block_product_needs_current_transposed_pages():
+    """The block product reads A's transposed pages: refused while they are
+    stale, and with page-layout values it equals the product of a handle
+    built from the same values."""
+    op = random_pattern(seed=9, n=20, bset=(2, 5, 9), density=0.3)
+    A = Matrix.from_operator(op)
+    P = A.get_pages()
+    B = Matrix.from_operator(op, values=np.zeros(op.nnz))
+    B.use_pages(P)
+    with pytest.raises(VbcsrError):
+        B.spgemm(B, 0.0)
+    B.refresh_transposed()
+    C1, _ = A.spgemm(A, 0.0)
+    C2, _ = B.spgemm(B, 0.0)
+    assert np.array_equal(C1.row_ptr, C2.row_ptr) and np.array_equal(C1.col_idx, C2.col_idx)
+    assert torch.equal(C1.values(), C2.values())
