@@ -1654,6 +1654,143 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4
   }
 }
 
+// The same in FP32 (nrhs = 32 NCH): a step is one tile and one 32-wide chunk
+// of right-hand sides, whose 16 X row pieces (128 bytes each, 2 KiB) arrive
+// by two buffer-to-LDS loads: lane l of load it fetches 16-byte piece
+// (l & 7) ^ (r & 7) of row r = 8 it + (l >> 3), so row r sits at r * 128
+// bytes with its pieces permuted and the fragment reads of 16 rows at one
+// piece index spread over the banks.  Lane (m, kq) holds right-hand sides
+// 8 kq .. 8 kq + 7 of each chunk for both operands (two pieces of its row;
+// the contraction order inside a chunk is permuted, the sum is the same).
+// A tile's outputs are stored during the first step of the next tile, after
+// that step's loads are issued.  Requires X within 2^31 bytes, 16-byte
+// aligned rows.
+template <int NCH, bool PAGE>
+__global__ void __launch_bounds__(kThreads) k_sddmm_dma32(SddmmParams<float> P) {
+  using LdsPtr = __attribute__((address_space(3))) void *;
+  constexpr int CW = 32;
+  __shared__ __align__(16) float xs_all[kWaves * 16 * CW];
+  const int row = xcd_remap(blockIdx.x, gridDim.x) * kWaves + wave_id();
+  if (row >= P.nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int m = lane & 15;
+  const int kq = lane >> 4;
+  float *xs = xs_all + wave_id() * 16 * CW;
+  const RowDesc rd = P.rows[row];
+  const int b = rd.b, K = rd.K;
+  if (K == 0) return;
+  const int ntiles = (K + 15) >> 4;
+  const int nsteps = ntiles * NCH;
+  const int64_t *__restrict__ cg = P.colg + rd.cbase;
+  const __amdgpu_buffer_rsrc_t rx =
+      panel_rsrc(P.X, (uint32_t)(P.xrows * P.ldx * (int64_t)sizeof(float)));
+  // the panel's indices rounded up to a group of four (four entries of slack)
+  const __amdgpu_buffer_rsrc_t rc =
+      panel_rsrc(P.colx + rd.cbase, (uint32_t)((K + 3) & ~3) * 4u);
+  const int lr = lane >> 3;   // this lane's rows of a step: lr and 8 + lr
+  auto rows_of = [&](int j) {
+    v2u32 r;
+    r.x = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)(j * 16 + lr) * 4u, 0, 0);
+    r.y = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rc, (uint32_t)(j * 16 + 8 + lr) * 4u, 0,
+                                                         0);
+    return r;
+  };
+  auto gmap_of = [&](int j) {
+    const int kk = min(j * 16 + m, K - 1);
+    return PAGE ? page_map(rd, kk) : cg[kk];
+  };
+  auto issue = [&](int s, v2u32 xr) {
+    const int j = s / NCH, ch = s % NCH;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int r = 8 * it + lr;
+      const int pc = (lane & 7) ^ (r & 7);
+      const uint32_t off =
+          j * 16 + r < K ? (uint32_t)(((int64_t)(int32_t)xr[it] * P.ldx + ch * CW + 4 * pc) *
+                                      (int64_t)sizeof(float))
+                         : 0x80000000u;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LdsPtr)(xs + it * 8 * CW), 16, off, 0, 0, 0);
+    }
+  };
+  const float *xm = xs + m * CW;   // row m in LDS
+  for (int mt = 0; mt * 16 < b; ++mt) {
+    const int p = mt * 16 + m;
+    const float *dyrow = P.dY + ((int64_t)rd.yrow + (p < b ? p : b - 1)) * P.lddy;
+    // A fragments: lane (m, kq) holds c = 32 ch + 8 kq + t
+    float af[NCH][8];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float v = dyrow[ch * CW + 8 * kq + t];
+        af[ch][t] = p < b ? v : 0.0f;
+      }
+    v2u32 xr_cur = rows_of(0), xr_nxt = rows_of(1), xr_nn = xr_nxt;
+    int64_t g_cur = gmap_of(0), g_nxt = gmap_of(1), g_nn = g_nxt, g_done = 0;
+    issue(0, xr_cur);
+    v4f acc0 = v4f{}, acc1 = v4f{};
+    float done[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int j = 0; j < ntiles; ++j) {
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) {
+        const int s = j * NCH + ch;
+        float bv[8];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const float4 v =
+              *reinterpret_cast<const float4 *>(xm + 4 * ((2 * kq + h) ^ (m & 7)));
+          bv[4 * h] = v.x;
+          bv[4 * h + 1] = v.y;
+          bv[4 * h + 2] = v.z;
+          bv[4 * h + 3] = v.w;
+        }
+        // the fragments are in registers before the buffer is refilled
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt, expcnt unchanged
+        if (ch == 0 && j > 0) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) done[i] = acc0[i] + acc1[i];
+          acc0 = v4f{};
+          acc1 = v4f{};
+          g_done = g_cur;
+          xr_cur = xr_nxt;
+          g_cur = g_nxt;
+          xr_nxt = xr_nn;
+          g_nxt = g_nn;
+        }
+        if (s + 1 < nsteps) issue(s + 1, ch == NCH - 1 ? xr_nxt : xr_cur);
+        if (ch == 0) {
+          xr_nn = rows_of(j + 2);
+          g_nn = gmap_of(j + 2);
+          if (j > 0) {   // outputs of tile j - 1 (a whole tile)
+            const int64_t base = g_done >> 7;
+            const int bj = (int)(g_done & 127);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int pr = mt * 16 + dst_row<float>(kq, i);
+              if (pr < b) P.dA[base + (int64_t)pr * bj] = done[i];
+            }
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+          acc0 = mfma(af[ch][t], bv[t], acc0);
+          acc1 = mfma(af[ch][t + 1], bv[t + 1], acc1);
+        }
+      }
+    }
+    // outputs of the last tile
+    if ((ntiles - 1) * 16 + m < K) {
+      const int64_t base = g_cur >> 7;
+      const int bj = (int)(g_cur & 127);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pr = mt * 16 + dst_row<float>(kq, i);
+        if (pr < b) P.dA[base + (int64_t)pr * bj] = acc0[i] + acc1[i];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // column dot products in FP64 and their fixed-order reduction
 // ---------------------------------------------------------------------------
@@ -2123,6 +2260,19 @@ hipError_t launch_sddmm_t(const SddmmParams<T> &p, hipStream_t s) {
         hipLaunchKernelGGL((k_sddmm_dma<2, true>), grid, dim3(kThreads), 0, s, pd);
       else
         hipLaunchKernelGGL((k_sddmm_dma<2, false>), grid, dim3(kThreads), 0, s, pd);
+      return hipGetLastError();
+    }
+    if (std::is_same<T, float>::value && (p.nrhs == 32 || p.nrhs == 64) &&
+        reinterpret_cast<uintptr_t>(p.X) % 16 == 0 && p.ldx % 4 == 0) {
+      const auto &pf = reinterpret_cast<const SddmmParams<float> &>(p);
+      if (p.nrhs == 32 && p.page_out)
+        hipLaunchKernelGGL((k_sddmm_dma32<1, true>), grid, dim3(kThreads), 0, s, pf);
+      else if (p.nrhs == 32)
+        hipLaunchKernelGGL((k_sddmm_dma32<1, false>), grid, dim3(kThreads), 0, s, pf);
+      else if (p.page_out)
+        hipLaunchKernelGGL((k_sddmm_dma32<2, true>), grid, dim3(kThreads), 0, s, pf);
+      else
+        hipLaunchKernelGGL((k_sddmm_dma32<2, false>), grid, dim3(kThreads), 0, s, pf);
       return hipGetLastError();
     }
     if (p.nrhs <= 32)
