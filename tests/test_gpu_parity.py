@@ -54,7 +54,7 @@ def test_fp64_forward_and_transpose(pattern, path, nrhs):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("nrhs", [1, 8, 16, 40, 100, 128])
+@pytest.mark.parametrize("nrhs", [1, 8, 16, 32, 40, 64, 100, 128])
 def test_reduced_precision_forward(pattern, prec, nrhs):
     name, op = pattern
     print("case", name, prec, nrhs, flush=True)
