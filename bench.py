@@ -425,7 +425,7 @@ def run_c2(args, checks, only):
 def main():
     args = parse()
     if args.gpus != 1:
-        sys.exit("bench.py measures one GPU only: this build has no multi-GPU path "
+        sys.exit("bench.py measures one GPU only: this library has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
     if args.spgemm or args.kpm or args.kspace or args.orders:
         recs = (spgemm_records(with_cpu=not args.no_cpu) if args.spgemm else []) + \

@@ -59,7 +59,7 @@ enum {
   VBCSR_EDUP = -3,         /* a block (i, j) appears twice in one row                   */
   VBCSR_ENOMEM = -4,       /* device or host allocation failed                          */
   VBCSR_EHIP = -5,         /* HIP runtime error (message holds hipGetErrorString)       */
-  VBCSR_EUNSUPPORTED = -6  /* valid but outside what this build handles                 */
+  VBCSR_EUNSUPPORTED = -6  /* valid but outside what this library handles               */
 };
 
 enum { VBCSR_PATH_AUTO = 0, VBCSR_PATH_VEC = 1, VBCSR_PATH_MFMA = 2 };
@@ -91,7 +91,7 @@ typedef struct {
   int32_t row_order;
 } vbcsr_plan_opts;
 
-/* Largest block size (orbitals per atom) this build accepts. */
+/* Largest block size (orbitals per atom) this library accepts. */
 #define VBCSR_MAX_BLOCK 64
 
 /*
