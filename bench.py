@@ -105,6 +105,9 @@ def parse():
                     help="time the products of C3 and C5 in each processing order and exit")
     ap.add_argument("--kspace", action="store_true",
                     help="only run the reciprocal-space operator records and print them")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="time plain 1 GiB fill, sum and copy kernels (write-only, read-only "
+                         "and read + write rates of this device) and exit")
     return ap.parse_args()
 
 
@@ -427,11 +430,12 @@ def main():
     if args.gpus != 1:
         sys.exit("bench.py measures one GPU only: this library has no multi-GPU path "
                  "(requested --gpus %d)" % args.gpus)
-    if args.spgemm or args.kpm or args.kspace or args.orders:
+    if args.spgemm or args.kpm or args.kspace or args.orders or args.ceilings:
         recs = (spgemm_records(with_cpu=not args.no_cpu) if args.spgemm else []) + \
             (kpm_records(with_cpu=not args.no_cpu) if args.kpm else []) + \
             (kspace_records() if args.kspace else []) + \
-            (order_records() if args.orders else [])
+            (order_records() if args.orders else []) + \
+            ([bandwidth_ceilings()] if args.ceilings else [])
         for rec in recs:
             print(json.dumps(rec), flush=True)
         return
@@ -526,6 +530,27 @@ def copy_calibration():
     torch.cuda.synchronize()
     return {"bytes_read": 1 << 30, "bytes_written": 1 << 30,
             "gbs": round(2 * (1 << 30) * 5 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)}
+
+
+def bandwidth_ceilings(reps=20):
+    """Rates of plain streaming kernels over 1 GiB (torch's fill, sum and
+    copy), medians of ``reps`` HIP-event timings after 3 untimed calls: the
+    write-only, read-only and read + write bandwidth this device reaches,
+    beside the 8 TB/s datasheet peak the roofline fractions use."""
+    import torch
+    dev = torch.device("cuda", 0)
+    n = 1 << 27
+    src = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    acc = torch.empty((), dtype=torch.float64, device=dev)
+    out = {"workload": "plain 1 GiB FP64 streams (torch fill_, sum, copy_)", "device": device_info()}
+    for name, fn, nbytes in (("fill_write_only", lambda: dst.fill_(2.0), n * 8),
+                             ("sum_read_only", lambda: torch.sum(src, dim=0, out=acc), n * 8),
+                             ("copy_read_write", lambda: dst.copy_(src), 2 * n * 8)):
+        ms = _time_call(fn, warm=3, reps=reps)
+        out[name] = {"ms": round(ms, 4), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_8tbs": round(nbytes / (ms * 1e-3) / 8e12, 4)}
+    return out
 
 
 def device_info():
