@@ -250,10 +250,11 @@ class Matrix:
         return n.value
 
     def _pages_arg(self, pages, name):
-        if not (isinstance(pages, torch.Tensor) and pages.is_cuda and pages.dtype == self.dtype
-                and pages.dim() == 1 and pages.is_contiguous() and pages.numel() == self.page_size):
-            raise ValueError("%s must be a contiguous CUDA %s tensor of %d entries"
-                             % (name, self.dtype, self.page_size))
+        if not (isinstance(pages, torch.Tensor) and pages.is_cuda and pages.device == self.device
+                and pages.dtype == self.dtype and pages.dim() == 1 and pages.is_contiguous()
+                and pages.numel() == self.page_size):
+            raise ValueError("%s must be a contiguous %s tensor of %d entries on %s"
+                             % (name, self.dtype, self.page_size, self.device))
         return pages
 
     def get_pages(self):
