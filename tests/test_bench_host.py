@@ -1,7 +1,8 @@
 """Host-side checks of the benchmark harness (no GPU): the one-GPU refusal,
 the algorithmic byte model against a brute-force count over the blocks, the
-roofline object's choice of bound, and the rule that a counter-based
-traffic figure is reported only for the kernel sources it was taken on."""
+roofline object's choice of bound, the rule that a counter-based traffic
+figure is reported only for the kernel sources it was taken on, and that
+every profile summary's command runs files of the repository."""
 import importlib.util
 import json
 import os
@@ -106,3 +107,25 @@ def test_committed_counter_summaries_name_their_sources(bench):
         assert len(rec["sha"]) == 16 and rec["kernels"]
         for k in rec["kernels"].values():
             assert k["fetch_bytes"] > 0 and k["write_bytes"] > 0
+
+
+def test_profile_commands_run_committed_files_only():
+    """Every profile summary gives the command that made it; the scripts
+    those commands run are files of the repository, never working files."""
+    import re
+    import glob
+    prof = sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md")))
+    assert prof
+    for path in prof:
+        text = open(path).read()
+        blocks = re.findall(r"```\n(.*?)```", text, re.S)
+        cmds = [l for b in blocks for l in b.splitlines() if "rocprofv3" in l]
+        assert cmds, "%s gives no rocprofv3 command" % os.path.basename(path)
+        for c in cmds:
+            assert "_work" not in c, c
+            prog = c.split(" -- ", 1)[1].split()
+            scripts = [t for t in prog if t.endswith((".py", ".sh"))]
+            assert scripts, c
+            for t in scripts:
+                rel = t.replace("$REPO/", "")
+                assert os.path.isfile(os.path.join(ROOT, rel)), (os.path.basename(path), t)
